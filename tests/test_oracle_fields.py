@@ -1,0 +1,216 @@
+"""Pins of the oracle's finite-difference fields: the tensorial stress equation (eqStiffCons with
+the corotational derivative, eqMaxDiff as its scalar limit) and the Beris-Edwards equation (eqBE),
+against exact discrete solutions, closed-form steady states and exact symmetries."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2209_14889_amd import workload as wl
+from tests.helpers import oracle_sim
+from tests.test_oracle_closure import quadrature_stiffness
+
+SCALAR_K = 0.02
+SCALAR_KX = (SCALAR_K, 0.0, SCALAR_K, SCALAR_K / 2)   # C~12 = 0: C~ = K I at P = 0
+
+
+def heun_factor(z):
+    return 1.0 + z + 0.5 * z * z
+
+
+def test_uniform_stress_relaxation_exact():
+    # sigma uniform, P = 0, no flow: d sigma/dt = -(K/eta_p) sigma; Heun gives the factor
+    # 1 + z + z^2/2 per step with z = -K/eta_p, and exp(-t K/eta_p) to O(z^3) per step
+    relax = 50.0
+    s0 = np.array([1e-3, -4e-4, 2.5e-4])
+    sig = np.broadcast_to(s0[:, None, None], (3, 12, 10)).copy()
+    s = oracle.Sim(dict(nx=10, ny=12, Kx=SCALAR_KX, eta_p=SCALAR_K * relax, D_p=0.05), sigma=sig)
+    s.run(100)
+    expect = s0 * heun_factor(-1.0 / relax) ** 100
+    assert np.max(np.abs(s.sigma - expect[:, None, None])) < 1e-13 * np.abs(s0).max()
+    assert np.max(np.abs(s.observe()["vx"])) < 1e-18
+    assert abs(expect[0] / (s0[0] * math.exp(-100 / relax)) - 1) < 100 * (1 / relax) ** 3 / 6 * 1.05
+
+
+def test_tensorial_relaxation_matrix():
+    # uniform P at the Beris-Edwards fixed point |P| = sqrt(-alpha/beta), no flow:
+    # sigma_n = (I + Z + Z^2/2)^n sigma_0 with Z = -C~(P)/eta_p (C~ from quadrature)
+    th = 0.7
+    Peq = math.sqrt(0.9)
+    Kx = (0.01, 0.005, 0.005, 0.005)
+    P = np.zeros((2, 9, 11)); P[0] = Peq * math.cos(th); P[1] = Peq * math.sin(th)
+    s0 = np.array([2e-3, -1e-3, 7e-4])
+    sig = np.broadcast_to(s0[:, None, None], (3, 9, 11)).copy()
+    eta = 0.5
+    s = oracle.Sim(dict(nx=11, ny=9, Kx=Kx, eta_p=eta, D_p=0.05), sigma=sig, P=P)
+    s.run(60)
+    C = quadrature_stiffness(Peq * math.cos(th), Peq * math.sin(th), Kx)
+    Z = -C / eta
+    G = np.eye(3) + Z + Z @ Z / 2
+    expect = np.linalg.matrix_power(G, 60) @ s0
+    assert np.max(np.abs(s.sigma[:, 4, 5] - expect)) < 1e-12 * np.abs(s0).max()
+    assert np.max(np.abs(s.sigma - s.sigma[:, :1, :1])) < 1e-17
+
+
+@pytest.mark.parametrize("m", [1, 3])
+def test_stress_diffusion_mode_decay(m):
+    # sigma_yy = A sin(k x) is divergence free (no flow); with no relaxation the discrete Laplacian
+    # gives z = -4 D sin^2(k/2) and the Heun factor per step; -> exp(-D k^2 t) as k -> 0
+    n, D, A = 48, 0.07, 1e-3
+    k = 2 * np.pi * m / n
+    x = np.arange(n)
+    sig = np.zeros((3, 6, n)); sig[1] = A * np.sin(k * x)[None, :]
+    s = oracle.Sim(dict(nx=n, ny=6, Kx=SCALAR_KX, eta_p=math.inf, D_p=D), sigma=sig)
+    s.run(80)
+    fac = heun_factor(-4 * D * math.sin(k / 2) ** 2) ** 80
+    assert np.max(np.abs(s.sigma[1] - fac * sig[1])) < 1e-13 * A
+    assert np.max(np.abs(s.sigma[0])) < 1e-18 and np.max(np.abs(s.sigma[2])) < 1e-18
+    if m == 1:
+        assert abs(fac / math.exp(-D * k * k * 80) - 1) < 5e-3
+
+
+def _shear_flow(n, rate):
+    y = np.arange(n)
+    vx = rate * n / (2 * np.pi) * np.sin(2 * np.pi * y / n)
+    u = np.zeros((2, n, 4)); u[0] = vx[:, None]
+    g = (np.roll(vx, -1) - np.roll(vx, 1)) / 2.0      # the discrete shear rate of each row
+    return u, g
+
+
+def test_corotational_maxwell_steady_shear():
+    # kinematic shear flow v_x(y): rows decouple; the steady corotational Maxwell stress with
+    # mu = K/eta_p and Wi = gdot/mu is sigma_xy = (K/2) Wi/(1 + Wi^2),
+    # sigma_xx = -sigma_yy = gdot sigma_xy / mu
+    n, mu = 32, 0.05
+    u, g = _shear_flow(n, 0.08)
+    s = oracle.Sim(dict(nx=4, ny=n, Kx=SCALAR_KX, eta_p=SCALAR_K / mu, D_p=0.0, kinematic=1,
+                        evolve_P=0), u_kin=u)
+    s.run(1500)
+    Wi = g / mu
+    sxy = SCALAR_K / 2 * Wi / (1 + Wi * Wi)
+    sxx = g * sxy / mu
+    scale = np.abs(sxx).max()
+    assert np.max(np.abs(s.sigma[2][:, 0] - sxy)) < 1e-10 * scale
+    assert np.max(np.abs(s.sigma[0][:, 0] - sxx)) < 1e-10 * scale
+    assert np.max(np.abs(s.sigma[1][:, 0] + sxx)) < 1e-10 * scale
+
+
+def test_flow_alignment_leslie_angle():
+    # eqBE in simple shear: d theta/dt = (gdot/2)(xi cos 2theta - 1), so the director settles at
+    # cos 2 theta = 1/xi where the shear rate is positive
+    n, xi = 32, 1.1
+    u, g = _shear_flow(n, 0.1)
+    P = np.zeros((2, n, 4)); P[0] = math.sqrt(0.9)
+    s = oracle.Sim(dict(nx=4, ny=n, xi=xi, kappa=0.0, kinematic=1, evolve_sigma=0), P=P, u_kin=u)
+    s.run(4000)
+    th = np.arctan2(s.P[1][:, 0], s.P[0][:, 0])
+    rows = g > 0.03
+    assert rows.sum() > 8
+    assert np.max(np.abs(th[rows] - 0.5 * math.acos(1 / xi))) < 1e-8
+
+
+def test_beris_edwards_magnitude_logistic():
+    # uniform P, no flow: s = |P|^2 obeys ds/dt = r s (1 - s/s_K), r = -2 Gamma alpha,
+    # s_K = -alpha/beta; the equilibrium sqrt(-alpha/beta) is a fixed point
+    Gamma, alpha, beta = 0.01, -0.9, 1.0
+    P = np.zeros((2, 5, 5)); P[0] = 0.1 * math.cos(0.4); P[1] = 0.1 * math.sin(0.4)
+    s = oracle.Sim(dict(nx=5, ny=5, Gamma=Gamma, alpha=alpha, beta=beta, kinematic=1,
+                        evolve_sigma=0), P=P)
+    s.run(300)
+    r, sK, s0 = -2 * Gamma * alpha, -alpha / beta, 0.01
+    ref = sK / (1 + (sK / s0 - 1) * math.exp(-r * 300))
+    got = s.P[0, 2, 2] ** 2 + s.P[1, 2, 2] ** 2
+    assert abs(got / ref - 1) < 1e-4
+    assert abs(math.atan2(s.P[1, 2, 2], s.P[0, 2, 2]) - 0.4) < 1e-15
+    Peq = math.sqrt(-alpha / beta)
+    P2 = np.zeros((2, 5, 5)); P2[0] = Peq
+    s2 = oracle.Sim(dict(nx=5, ny=5, Gamma=1.0, alpha=alpha, beta=beta, kinematic=1, evolve_sigma=0), P=P2)
+    s2.run(50)
+    assert abs(s2.P[0, 0, 0] - Peq) < 1e-15
+
+
+def _mirror_state(h, sig, P):
+    """y -> -y on the periodic lattice: sites (x, y) -> (x, (-y) mod ny), links c -> (cx, -cy)."""
+    perm = [0, 1, 4, 3, 2, 8, 7, 6, 5]
+    def fy(a):
+        return np.roll(a[..., ::-1, :], 1, axis=-2)
+    hm = np.stack([fy(h[perm[n]]) for n in range(9)])
+    sm = np.stack([fy(sig[0]), fy(sig[1]), -fy(sig[2])])
+    Pm = np.stack([fy(P[0]), -fy(P[1])])
+    return hm, sm, Pm
+
+
+def test_y_mirror_symmetry_of_coupled_run():
+    w = wl.small_case(31, 30, 28, n_bodies=1, radius=4.0, pull=2e-4)
+    a = oracle_sim(w.sims[0])
+    b = oracle_sim(w.sims[0])
+    ny = a.p.ny
+    b.h, b.sigma, b.P = [np.ascontiguousarray(x) for x in _mirror_state(a.h, a.sigma, a.P)]
+    bb = b.bodies[0]
+    R = bb.R.copy(); R[:, 1] = -R[:, 1] + ny
+    bb.R = np.ascontiguousarray(R[::-1])
+    bb.pull = (bb.pull[0], -bb.pull[1])
+    a.run(40); b.run(40)
+    hm, sm, Pm = _mirror_state(a.h, a.sigma, a.P)
+    assert np.max(np.abs(b.h - hm)) < 1e-13
+    assert np.max(np.abs(b.sigma - sm)) < 1e-12 * np.abs(a.sigma).max()
+    assert np.max(np.abs(b.P - Pm)) < 1e-12
+    Rm = a.bodies[0].R.copy(); Rm[:, 1] = -Rm[:, 1] + ny
+    assert np.max(np.abs(bb.R - Rm[::-1])) < 1e-11
+
+
+def test_polarization_sign_symmetry():
+    # eqBE is odd in P, the Ericksen stress and C~(P) are even: P -> -P leaves the flow and the
+    # stress unchanged and flips P
+    w = wl.small_case(32, 24, 22, n_bodies=1, radius=4.0)
+    a = oracle_sim(w.sims[0])
+    b = oracle_sim(w.sims[0])
+    b.P = -b.P
+    a.run(30); b.run(30)
+    assert np.max(np.abs(a.h - b.h)) < 1e-14
+    assert np.max(np.abs(a.sigma - b.sigma)) < 1e-12 * np.abs(a.sigma).max()
+    assert np.max(np.abs(a.P + b.P)) < 1e-12
+
+
+def test_restoring_force_sums_to_zero_over_domain():
+    w = wl.small_case(33, 26, 24, n_bodies=1, radius=4.0)
+    s = oracle_sim(w.sims[0])
+    s.run(30)
+    o = s.observe()
+    scale = np.abs(o["fpx"]).max()
+    assert abs(o["fpx"].sum()) < 1e-13 * scale * o["fpx"].size
+    assert abs(o["fpy"].sum()) < 1e-13 * scale * o["fpy"].size
+
+
+def _free_energy(P, alpha, beta, kappa):
+    s = P[0] ** 2 + P[1] ** 2
+    grad = sum(((np.roll(P[c], -1, axis=a) - P[c]) ** 2).sum() for c in range(2) for a in range(2))
+    return (alpha / 2 * s + beta / 4 * s * s).sum() + kappa / 2 * grad
+
+
+def test_ericksen_coupling_dissipates_energy():
+    # undriven periodic run with the polymer stress off: free energy (eqFfunctional) plus kinetic
+    # energy decays; a flipped sign or a missing kappa in the Ericksen stress makes it grow
+    w = wl.small_case(34, 32, 32, n_bodies=0, random_dirs=True)
+    s = oracle_sim(w.sims[0], polymer_force=0, evolve_sigma=0)
+    p = s.pdict
+    E = []
+    for _ in range(12):
+        o = s.observe()
+        ke = 0.5 * (o["rho"] * (o["vx"] ** 2 + o["vy"] ** 2)).sum()
+        E.append(_free_energy(s.P, p["alpha"], p["beta"], p["kappa"]) + ke)
+        s.run(10)
+    E = np.array(E)
+    assert E[-1] < E[0]
+    assert np.all(np.diff(E) < 1e-9 * abs(E[0]))
+
+
+def test_kinematic_uniform_translation_of_nodes():
+    n = 20
+    u = np.zeros((2, n, n)); u[0] = 0.013; u[1] = -0.007
+    R = oracle.polygon(10.0, 9.0, 4.0, 16)
+    s = oracle.Sim(dict(nx=n, ny=n, kinematic=1, evolve_sigma=0, evolve_P=0),
+                   bodies=[oracle.Body(R=R.copy())], u_kin=u)
+    s.run(25)
+    assert np.max(np.abs(s.bodies[0].R - (R + 25 * np.array([0.013, -0.007])))) < 1e-13

@@ -1,0 +1,117 @@
+"""Pins of the oracle's immersed-boundary parts (App. A): the cosine kernel, spreading and
+interpolation, and the node forces as the gradient of an independently written energy."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+
+def test_phi_definition_points():
+    assert oracle.phi(0.0) == 0.5
+    assert abs(oracle.phi(1.0) - 0.25) < 1e-17
+    assert abs(oracle.phi(-1.0) - 0.25) < 1e-17
+    assert oracle.phi(2.0) == 0.0 and oracle.phi(-2.5) == 0.0
+    for r in np.linspace(-1.99, 1.99, 37):
+        assert abs(oracle.phi(r) - 0.25 * (1 + math.cos(math.pi * r / 2))) < 1e-16
+
+
+def test_kernel_partition_of_unity_brute_force():
+    # sum over every lattice site of phi(Rx - x) phi(Ry - y) = 1 for any R (periodic 16x16)
+    rng = np.random.default_rng(11)
+    s = oracle.Sim(dict(nx=16, ny=16))
+    for _ in range(50):
+        R = rng.uniform(0, 16, size=(1, 2))
+        fx, fy = s.spread(R, np.array([[1.0, 0.0]]))
+        assert abs(fx.sum() - 1.0) < 1e-15 and np.all(fy == 0)
+        # brute force over every site, minimum image
+        tot = 0.0
+        for y in range(16):
+            for x in range(16):
+                dx = (R[0, 0] - x + 8) % 16 - 8
+                dy = (R[0, 1] - y + 8) % 16 - 8
+                tot += oracle.phi(dx) * oracle.phi(dy)
+        assert abs(tot - 1.0) < 1e-15
+
+
+def test_spread_interp_adjoint():
+    # sum_r f_IB(r) . u(r) = sum_a f_a . u^I(R_a)
+    rng = np.random.default_rng(12)
+    s = oracle.Sim(dict(nx=24, ny=20))
+    R = rng.uniform(-30, 50, size=(17, 2))
+    f = rng.normal(size=(17, 2))
+    ux, uy = rng.normal(size=(20, 24)), rng.normal(size=(20, 24))
+    fx, fy = s.spread(R, f)
+    lhs = (fx * ux).sum() + (fy * uy).sum()
+    rhs = (f * s.interp(R, ux, uy)).sum()
+    assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
+
+
+def test_interp_of_uniform_field_is_exact():
+    rng = np.random.default_rng(13)
+    s = oracle.Sim(dict(nx=16, ny=16))
+    R = rng.uniform(0, 16, size=(9, 2))
+    v = s.interp(R, np.full((16, 16), 0.3), np.full((16, 16), -0.7))
+    assert np.max(np.abs(v - np.array([0.3, -0.7]))) < 1e-15
+
+
+def _energy_numpy(R, k, eps, leq):
+    """Energy of App. A (eqConst without the trap): springs k/2 (l_a - l_eq)^2 with
+    l_a = |R_{a+1} - R_a|, bending eps (1 - cos(pi - gamma_a))."""
+    n = len(R)
+    U = 0.0
+    for a in range(n):
+        d = R[(a + 1) % n] - R[a]
+        U += 0.5 * k * (np.hypot(*d) - leq) ** 2
+    for a in range(n):
+        e1 = R[(a - 1) % n] - R[a]
+        e2 = R[(a + 1) % n] - R[a]
+        gam = math.acos(np.clip(e1 @ e2 / (np.hypot(*e1) * np.hypot(*e2)), -1, 1))
+        U += eps * (1 - math.cos(math.pi - gam))
+    return U
+
+
+def test_node_forces_are_minus_energy_gradient():
+    rng = np.random.default_rng(14)
+    n = 12
+    R0 = oracle.polygon(5.0, 6.0, 3.0, n) + rng.normal(scale=0.15, size=(n, 2))
+    k, eps, leq = 0.07, 0.013, 1.4
+    b = oracle.Body(R=R0.copy(), k_spring=k, eps_angle=eps, l_eq=leq)
+    f = b.forces()
+    h = 1e-6
+    for a in range(n):
+        for c in range(2):
+            Rp = R0.copy(); Rp[a, c] += h
+            Rm = R0.copy(); Rm[a, c] -= h
+            g = (_energy_numpy(Rp, k, eps, leq) - _energy_numpy(Rm, k, eps, leq)) / (2 * h)
+            assert abs(f[a, c] + g) < 1e-8, (a, c, f[a, c], -g)
+    assert abs(b.energy() - _energy_numpy(R0, k, eps, leq)) < 1e-14
+
+
+def test_internal_forces_sum_and_torque_vanish():
+    rng = np.random.default_rng(15)
+    n = 20
+    R0 = oracle.polygon(0.0, 0.0, 4.0, n) + rng.normal(scale=0.3, size=(n, 2))
+    b = oracle.Body(R=R0, k_spring=0.05, eps_angle=0.02, l_eq=1.1)
+    f = b.forces()
+    assert np.max(np.abs(f.sum(axis=0))) < 1e-15
+    torque = np.sum(R0[:, 0] * f[:, 1] - R0[:, 1] * f[:, 0])
+    assert abs(torque) < 1e-14
+
+
+def test_regular_polygon_rest_state_and_pull_share():
+    from paper_2209_14889_amd import workload as wl
+    spec = wl.make_body(10.0, 10.0, 6.0, 40, (1e-4, -2e-4))
+    b = oracle.Body(R=spec.R, k_spring=spec.k_spring, eps_angle=spec.eps_angle, l_eq=spec.l_eq,
+                    pull=spec.pull)
+    f = b.forces()
+    assert np.max(np.abs(f - np.array([1e-4, -2e-4]) / 40)) < 1e-14
+
+
+def test_pull_schedule_logistic():
+    b = oracle.Body(R=oracle.polygon(0, 0, 3, 8), pull=(1.0, 0.0), t_on=120, t_off=2048, width=30)
+    assert abs(b.pull_factor(120) - (0.5 - 1 / (1 + math.exp(1928 / 30)))) < 1e-15
+    assert b.pull_factor(0) < 0.02 and b.pull_factor(1000) > 0.999 and b.pull_factor(4000) < 1e-20
+    b2 = oracle.Body(R=oracle.polygon(0, 0, 3, 8), pull=(1.0, 0.0))
+    assert b2.pull_factor(12345) == 1.0
