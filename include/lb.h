@@ -1,0 +1,156 @@
+/*
+ * liblb: MI355X (gfx950) library for the coupled viscoelastic immersed-boundary lattice
+ * Boltzmann step of Floyd, Vaikuntanathan and Dinner, "Simulating structured fluids with
+ * tensorial viscoelasticity" (arXiv 2209.14889).
+ *
+ * The problem (abstract, Sec. II): an elastic body immersed in a structured fluid is driven by an
+ * external force.  The state is {h_n (fluid populations), sigma^p (polymer stress), P
+ * (polarization), R_a (body nodes)} (Fig. 2).  One step updates every field from the previous
+ * time step: D2Q9 BGK collide-stream with Guo forcing by F = f_IB + div sigma^p + div sigma^E
+ * (Sec. II A-C, App. A), Heun predictor-corrector for sigma^p (eqStiffCons, corotational) and P
+ * (eqBE), and overdamped no-slip node motion (App. A).
+ *
+ * Conventions for every entry point:
+ *   - return 0 (LB_OK) on success or a negative LB_E* code; lb_last_error() then holds a message
+ *     for the calling thread;
+ *   - lattice units (dx = dt = 1); fields are planes of ny*nx values with x fastest;
+ *   - host pointers are read during the call only and are never retained; device memory is the
+ *     caller-owned arena passed to lb_create, which the library never frees;
+ *   - a handle is bound to one HIP stream and is not thread safe; lb_step is asynchronous, and
+ *     faults of its kernels (LB_EDEVICE) or a raised watchdog (LB_EUNSTABLE) are reported by the
+ *     next synchronising call (lb_read_fields, lb_body_force, lb_conservation, lb_sync) and by
+ *     later lb_step calls;
+ *   - no C++ exception crosses the boundary; null pointers are rejected with LB_EINVAL.
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_OK 0
+#define LB_EINVAL (-1)     /* invalid argument or parameter (see lb_create) */
+#define LB_ENOMEM (-2)     /* arena too small */
+#define LB_EDEVICE (-3)    /* HIP runtime error */
+#define LB_EUNSTABLE (-4)  /* watchdog: non-finite or drifting mass */
+#define LB_ERANGE (-5)     /* index out of range, or a body outgrew its force patch */
+
+typedef struct lb_handle lb_handle;
+
+/* One immersed elastic body (App. A): a closed loop of n_nodes points with springs
+ * k_spring/2 (l_a - l_eq)^2 and bending eps_angle (1 - cos(pi - gamma_a)).  The external drive
+ * is a total force (pull_fx, pull_fy) shared equally by the nodes, optionally switched on and
+ * off by logistic functions of time (App. C: sigmoid protocol) of scale pull_width steps centred
+ * at pull_t_on and pull_t_off; pull_width <= 0 means a constant pull. */
+typedef struct {
+    double cx, cy, radius;      /* regular polygon, node a at angle 2 pi a / n_nodes */
+    int32_t n_nodes;            /* 3 .. 1024 */
+    double k_spring, eps_angle, l_eq;
+    double pull_fx, pull_fy;
+    double pull_t_on, pull_t_off, pull_width;
+    const double *nodes;        /* optional host array of 2*n_nodes unwrapped positions
+                                   (x0, y0, x1, y1, ...) replacing the polygon; may be NULL */
+} lb_body_desc;
+
+/* One simulation on a periodic nx x ny lattice. */
+typedef struct {
+    int32_t nx, ny;             /* 8 .. 16384 each */
+    double tau;                 /* BGK relaxation time (eqBGK), > 0.5 */
+    double Kx[4];               /* K1111, K1122, K2222, K1212 of the aligned stiffness (eqKmatrix) */
+    double eta_p;               /* polymer viscosity (eqStiffCons), > 0 (may be +inf) */
+    double D_p;                 /* stress diffusion, 0 <= D_p < 0.25 (Heun stability) */
+    double xi, alpha, beta, kappa, Gamma;  /* Beris-Edwards and free energy (eqBE, eqFfunctional) */
+    double P_clamp;             /* magnitude cap when inverting P(k) (eqPk), in (0, 1) */
+    int32_t ericksen;           /* 1: the Ericksen force enters F (the paper's model) */
+    int32_t n_bodies;           /* 0 .. 64 */
+    const lb_body_desc *bodies;
+    const double *init_P;       /* host 2*nx*ny (Px plane, Py plane) or NULL (P = 0) */
+    const double *init_sigma;   /* host 3*nx*ny (sxx, syy, sxy) or NULL (sigma = 0) */
+    const double *init_h;       /* host 9*nx*ny pre-collision populations or NULL (rest state) */
+} lb_sim_params;
+
+typedef struct {
+    int32_t precision;          /* 0: FP32 populations stored as offsets from the rest weights;
+                                   1: FP16 storage of those offsets times 2^fp16_shift (FP32 math) */
+    int32_t fp16_shift;         /* 0 selects the default 10 */
+    int32_t watchdog_every;     /* FP64 mass / finiteness check every this many steps; 0 = off */
+    int32_t graph_chunk;        /* steps captured per hipGraph (even); 0 = plain launches */
+    int32_t kernel;             /* 0: fused single-pass field kernel; 1: multi-pass kernels */
+    int32_t timing;             /* 1: time every field-kernel launch with HIP events */
+    int32_t seg_rows;           /* rows per fused work item; 0 = tuned default */
+    int32_t fused_threads;      /* fused work-group size: 128 or 256 (strip of 120 or 248
+                                   columns); 0 = chosen from the lattice width */
+    int32_t reserved[4];
+} lb_options;
+
+/* Bytes of device memory lb_create needs for these simulations (arena for all state, tables,
+ * patches and scratch).  sims: n_sims parameter sets; opt may be NULL (defaults). */
+int lb_query_arena_bytes(const lb_sim_params *sims, int32_t n_sims, const lb_options *opt,
+                         size_t *bytes);
+
+/* Create a handle for n_sims independent simulations advanced together (n_sims > 1 is the
+ * batched ensemble; sizes may differ).  device_arena: caller-owned device memory of at least
+ * lb_query_arena_bytes bytes, 256-byte aligned.  hip_stream: the stream (hipStream_t) all work
+ * is issued on; NULL makes the library create its own.  Validates: tau > 0.5, 8 D_p < 2,
+ * 0 < P_clamp < 1, eta_p > 0, sizes, node counts, and that every body's force patch fits the
+ * lattice.  Uploads the initial state and spreads the initial body forces; synchronous. */
+int lb_create(const lb_sim_params *sims, int32_t n_sims, const lb_options *opt,
+              void *device_arena, size_t arena_bytes, void *hip_stream, lb_handle **out);
+
+/* Advance every simulation by n_steps >= 0 coupled steps (asynchronous on the stream). */
+int lb_step(lb_handle *h, int32_t n_steps);
+
+/* Field selection bits for lb_read_fields, in output order. */
+#define LB_F_RHO   (1u << 0)   /* density, sum h (eqrhoDef) */
+#define LB_F_VX    (1u << 1)   /* velocity (sum c h + F/2)/rho (eqvDef with Guo's half force) */
+#define LB_F_VY    (1u << 2)
+#define LB_F_SXX   (1u << 3)   /* polymer stress */
+#define LB_F_SYY   (1u << 4)
+#define LB_F_SXY   (1u << 5)
+#define LB_F_PX    (1u << 6)   /* polarization */
+#define LB_F_PY    (1u << 7)
+#define LB_F_FPX   (1u << 8)   /* restoring force density div sigma^p (Figs. 5, 6, 10) */
+#define LB_F_FPY   (1u << 9)
+#define LB_F_NODES (1u << 10)  /* all bodies' node positions, 2 per node, body by body */
+#define LB_F_ALL   0x7FFu
+
+/* Read the selected fields of simulation `sim` at the current time into host_out (FP64):
+ * each selected plane is ny*nx values, planes in bit order, then the nodes if selected.
+ * n_out is the capacity of host_out in doubles (LB_ERANGE if too small).  Synchronous. */
+int lb_read_fields(lb_handle *h, int32_t sim, uint32_t field_mask, double *host_out, size_t n_out);
+
+/* Body observables at the current time, FP64 (synchronous):
+ * out[0..1] restoring force: sum of div sigma^p over the lattice sites inside the node polygon;
+ * out[2..3] the current external pull; out[4..5] centre of mass of the nodes;
+ * out[6..7] total force the nodes apply to the fluid (sum_a f_a). */
+int lb_body_force(lb_handle *h, int32_t sim, int32_t body, double out[8]);
+
+/* FP64 conservation sums of simulation `sim` at the current time (synchronous):
+ * out[0] = sum rho, out[1..2] = sum of sum_n c_n h_n (momentum without the half force). */
+int lb_conservation(lb_handle *h, int32_t sim, double out[3]);
+
+/* Wait for all queued work; reports deferred device errors and the watchdog. */
+int lb_sync(lb_handle *h);
+
+/* Steps taken so far. */
+int lb_time(lb_handle *h, int64_t *t);
+
+/* With opt.timing = 1: total milliseconds and number of field-kernel launches timed so far, and
+ * the same for the immersed-boundary kernel; counters reset when reset != 0.  Synchronous. */
+int lb_timing(lb_handle *h, double *field_ms, int64_t *field_launches, double *ib_ms,
+              int64_t *ib_launches, int32_t reset);
+
+/* Release the handle's host resources (and its stream if the library created it). */
+int lb_destroy(lb_handle *h);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *lb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

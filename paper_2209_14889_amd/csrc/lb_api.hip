@@ -1,0 +1,916 @@
+// Host runtime and C-ABI of liblb (declared in include/lb.h).
+//
+// The caller owns one device arena; lb_create carves every buffer out of it (state ping-pong
+// planes, stiffness tables, body patches, scratch), builds the work tables for the kernels and
+// uploads the initial state.  lb_step queues kernels (optionally replaying a captured hipGraph);
+// synchronising calls report deferred device errors and the watchdog.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lb.h"
+#include "lb_common.h"
+#include "lb_launch.h"
+
+using namespace lbk;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return fail(LB_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------------------------
+// stiffness tables: a2/s and a4/s^2 of the von Mises closure on a uniform grid in s = |P|^2.
+// The moments a_n(k) = <cos n theta> of g(theta; k) ~ exp(k cos theta) (Sec. II C 3) are
+// evaluated by the trapezoid rule on a periodic grid (spectrally accurate), and k(P) solves
+// <cos theta> = P by Newton's method with d<cos>/dk = <cos^2> - <cos>^2.
+// ---------------------------------------------------------------------------------------------
+
+struct VonMises {
+    static constexpr int M = 1024;
+    std::vector<double> c1, c2, c4;
+    VonMises() : c1(M), c2(M), c4(M) {
+        for (int j = 0; j < M; ++j) {
+            double th = 2.0 * M_PI * j / M;
+            c1[j] = std::cos(th);
+            c2[j] = std::cos(2.0 * th);
+            c4[j] = std::cos(4.0 * th);
+        }
+    }
+    // moments <cos theta>, <cos 2 theta>, <cos 4 theta>
+    void moments(double k, double &m1, double &m2, double &m4) const {
+        double z = 0, a = 0, b = 0, c = 0;
+        for (int j = 0; j < M; ++j) {
+            double w = std::exp(k * (c1[j] - 1.0));
+            z += w;
+            a += w * c1[j];
+            b += w * c2[j];
+            c += w * c4[j];
+        }
+        m1 = a / z;
+        m2 = b / z;
+        m4 = c / z;
+    }
+    double k_of_p(double p) const {
+        if (p <= 0.0) return 0.0;
+        // start: approximate inverse k ~ p (2 - p^2)/(1 - p^2) (Banerjee et al. 2005)
+        double k = p * (2.0 - p * p) / (1.0 - p * p), lo = 0.0, hi = 4.0 * k + 10.0;
+        for (int it = 0; it < 100; ++it) {
+            double m1, m2, m4;
+            moments(k, m1, m2, m4);
+            double f = m1 - p;
+            if (f > 0) hi = k; else lo = k;
+            double df = 0.5 * (1.0 + m2) - m1 * m1;
+            double kn = k - f / df;
+            if (!(kn > lo && kn < hi)) kn = 0.5 * (lo + hi);
+            bool done = std::fabs(kn - k) <= 1e-14 * std::max(1.0, k);
+            k = kn;
+            if (done) break;
+        }
+        return k;
+    }
+};
+
+struct Table {
+    std::vector<float4> rows;
+    double A2max, A4max;
+};
+
+const Table &stiffness_table(double P_clamp) {
+    static std::mutex mu;
+    static std::map<double, Table> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(P_clamp);
+    if (it != cache.end()) return it->second;
+    static const VonMises vm;
+    const double smax = P_clamp * P_clamp, ds = smax / kTab;
+    std::vector<double> A2(kTab + 1), A4(kTab + 1);
+    A2[0] = 0.5;            // a2 ~ k^2/8, s ~ k^2/4 as k -> 0
+    A4[0] = 1.0 / 24.0;     // a4 ~ k^4/384, s^2 ~ k^4/16
+    for (int i = 1; i <= kTab; ++i) {
+        double s = i * ds;
+        double k = vm.k_of_p(std::sqrt(s));
+        double m1, m2, m4;
+        vm.moments(k, m1, m2, m4);
+        A2[i] = m2 / s;
+        A4[i] = m4 / (s * s);
+    }
+    Table t;
+    t.rows.resize(kTab);
+    for (int i = 0; i < kTab; ++i)
+        t.rows[i] = make_float4((float)A2[i], (float)(A2[i + 1] - A2[i]), (float)A4[i], (float)(A4[i + 1] - A4[i]));
+    t.A2max = A2[kTab];
+    t.A4max = A4[kTab];
+    return cache.emplace(P_clamp, std::move(t)).first->second;
+}
+
+// ---------------------------------------------------------------------------------------------
+// arena layout
+// ---------------------------------------------------------------------------------------------
+
+struct Arena {
+    size_t off = 0;
+    char *base = nullptr;
+    size_t take(size_t bytes) {
+        size_t o = (off + 255) & ~(size_t)255;
+        off = o + bytes;
+        return o;
+    }
+    template <typename T> T *ptr(size_t o) const { return reinterpret_cast<T *>(base + o); }
+};
+
+struct BodyPlan {
+    int sim, n, ps, nside;
+    size_t oR0, oR1, oF, oOrigin, oFib, oVib;
+};
+
+struct SimPlan {
+    int nx, ny;
+    size_t N;
+    size_t oH0, oH1, oS0, oS1, oP0, oP1, oSE, oV, oSP;
+    int tab;     // index into the handle's table list
+    int blk0, nblk;
+};
+
+struct Plan {
+    std::vector<SimPlan> sims;
+    std::vector<BodyPlan> bodies;
+    std::vector<double> clamps;
+    std::vector<size_t> oTab;
+    size_t oSims, oBodies, oItems, oIbBlk, oSiteBlk, oT, oStatus, oPartial, oOut, oStage;
+    std::vector<WorkItem> items;
+    std::vector<int2> ib_blk;
+    std::vector<SiteBlock> site_blk;
+    int T = 256;
+    int max_partial = 1;
+    size_t bytes = 0;
+};
+
+struct Opt {
+    int precision = 0, shift = kDefaultShift, watchdog = 0, chunk = 0, kernel = 0, timing = 0, seg = 0, threads = 0;
+};
+
+Opt read_opt(const lb_options *o) {
+    Opt r;
+    if (!o) return r;
+    r.precision = o->precision;
+    r.shift = o->fp16_shift > 0 ? o->fp16_shift : kDefaultShift;
+    r.watchdog = o->watchdog_every;
+    r.chunk = o->graph_chunk;
+    r.kernel = o->kernel;
+    r.timing = o->timing;
+    r.seg = o->seg_rows;
+    r.threads = o->fused_threads;
+    return r;
+}
+
+double body_extent(const lb_body_desc &b) {
+    if (!b.nodes) return b.radius;
+    double cx = 0, cy = 0;
+    for (int a = 0; a < b.n_nodes; ++a) {
+        cx += b.nodes[2 * a];
+        cy += b.nodes[2 * a + 1];
+    }
+    cx /= b.n_nodes;
+    cy /= b.n_nodes;
+    double r = 0;
+    for (int a = 0; a < b.n_nodes; ++a)
+        r = std::max(r, std::hypot(b.nodes[2 * a] - cx, b.nodes[2 * a + 1] - cy));
+    return r;
+}
+
+int validate(const lb_sim_params *sims, int n_sims, const Opt &o) {
+    if (!sims || n_sims <= 0) return fail(LB_EINVAL, "need at least one simulation");
+    if (o.precision != 0 && o.precision != 1) return fail(LB_EINVAL, "precision must be 0 or 1");
+    if (o.shift < 0 || o.shift > 24) return fail(LB_EINVAL, "fp16_shift out of range");
+    if (o.kernel != 0 && o.kernel != 1) return fail(LB_EINVAL, "kernel must be 0 or 1");
+    if (o.chunk < 0 || (o.chunk & 1)) return fail(LB_EINVAL, "graph_chunk must be even and >= 0");
+    if (o.threads != 0 && o.threads != 128 && o.threads != 256) return fail(LB_EINVAL, "fused_threads must be 0, 128 or 256");
+    if (o.seg < 0) return fail(LB_EINVAL, "seg_rows must be >= 0");
+    for (int s = 0; s < n_sims; ++s) {
+        const lb_sim_params &p = sims[s];
+        if (p.nx < 8 || p.ny < 8 || p.nx > 16384 || p.ny > 16384) return fail(LB_EINVAL, "sim %d: lattice size out of range", s);
+        if (!(p.tau > 0.5)) return fail(LB_EINVAL, "sim %d: tau must exceed 0.5", s);
+        if (!(p.D_p >= 0.0) || !(8.0 * p.D_p < 2.0)) return fail(LB_EINVAL, "sim %d: need 0 <= D_p and 8 D_p < 2", s);
+        if (!(p.eta_p > 0.0)) return fail(LB_EINVAL, "sim %d: eta_p must be positive", s);
+        if (!(p.P_clamp > 0.0 && p.P_clamp < 1.0)) return fail(LB_EINVAL, "sim %d: P_clamp must be in (0, 1)", s);
+        if (p.n_bodies < 0 || p.n_bodies > kMaxBodies) return fail(LB_EINVAL, "sim %d: n_bodies out of range", s);
+        if (p.n_bodies > 0 && !p.bodies) return fail(LB_EINVAL, "sim %d: bodies is NULL", s);
+        for (int b = 0; b < p.n_bodies; ++b) {
+            const lb_body_desc &d = p.bodies[b];
+            if (d.n_nodes < 3 || d.n_nodes > kMaxNodes) return fail(LB_EINVAL, "sim %d body %d: n_nodes out of range", s, b);
+            if (!d.nodes && !(d.radius > 0.0)) return fail(LB_EINVAL, "sim %d body %d: radius must be positive", s, b);
+            double ext = body_extent(d);
+            int ps = 2 * (int)std::ceil(ext) + 24;
+            int lim = std::min(p.nx, p.ny);
+            if (2 * (int)std::ceil(ext) + 8 > lim)
+                return fail(LB_EINVAL, "sim %d body %d: body too large for the lattice", s, b);
+            (void)ps;
+        }
+    }
+    return LB_OK;
+}
+
+int pick_threads(const lb_sim_params *sims, int n_sims, const Opt &o) {
+    if (o.threads) return o.threads;
+    int mx = 0;
+    for (int s = 0; s < n_sims; ++s) mx = std::max(mx, sims[s].nx);
+    return mx <= 120 ? 128 : 256;
+}
+
+Plan make_plan(const lb_sim_params *sims, int n_sims, const Opt &o) {
+    Plan pl;
+    Arena a;
+    pl.T = pick_threads(sims, n_sims, o);
+    const size_t hb = o.precision == 1 ? 2 : 4;
+    int nblk_sites = 0;
+    size_t maxN = 0;
+    int total_bodies = 0;
+    for (int s = 0; s < n_sims; ++s) total_bodies += sims[s].n_bodies;
+    // distinct clamps -> tables
+    for (int s = 0; s < n_sims; ++s) {
+        double c = sims[s].P_clamp;
+        if (std::find(pl.clamps.begin(), pl.clamps.end(), c) == pl.clamps.end()) pl.clamps.push_back(c);
+    }
+    pl.oSims = a.take(sizeof(SimDev) * n_sims);
+    pl.oBodies = a.take(sizeof(BodyDev) * std::max(1, total_bodies));
+    for (size_t i = 0; i < pl.clamps.size(); ++i) pl.oTab.push_back(a.take(sizeof(float4) * kTab));
+    for (int s = 0; s < n_sims; ++s) {
+        const lb_sim_params &p = sims[s];
+        SimPlan sp;
+        sp.nx = p.nx;
+        sp.ny = p.ny;
+        sp.N = (size_t)p.nx * p.ny;
+        maxN = std::max(maxN, sp.N);
+        sp.oH0 = a.take(9 * sp.N * hb);
+        sp.oH1 = a.take(9 * sp.N * hb);
+        sp.oS0 = a.take(3 * sp.N * 4);
+        sp.oS1 = a.take(3 * sp.N * 4);
+        sp.oP0 = a.take(2 * sp.N * 4);
+        sp.oP1 = a.take(2 * sp.N * 4);
+        sp.oSE = a.take(4 * sp.N * 4);
+        sp.oV = a.take(o.kernel == 1 ? 2 * sp.N * 4 : 0);
+        sp.oSP = a.take(o.kernel == 1 ? 5 * sp.N * 4 : 0);
+        sp.tab = (int)(std::find(pl.clamps.begin(), pl.clamps.end(), p.P_clamp) - pl.clamps.begin());
+        sp.blk0 = nblk_sites;
+        sp.nblk = (int)((sp.N + 255) / 256);
+        for (int b = 0; b < sp.nblk; ++b) pl.site_blk.push_back(SiteBlock{s, b * 256});
+        nblk_sites += sp.nblk;
+        for (int b = 0; b < p.n_bodies; ++b) {
+            const lb_body_desc &d = p.bodies[b];
+            BodyPlan bp;
+            bp.sim = s;
+            bp.n = d.n_nodes;
+            bp.ps = std::min(2 * (int)std::ceil(body_extent(d)) + 24, std::min(p.nx, p.ny));
+            bp.nside = (bp.ps + kPatchTile - 1) / kPatchTile;
+            bp.oR0 = a.take(16 * (size_t)bp.n);
+            bp.oR1 = a.take(16 * (size_t)bp.n);
+            bp.oF = a.take(16 * (size_t)bp.n);
+            bp.oOrigin = a.take(4 * sizeof(int));
+            bp.oFib = a.take(2 * (size_t)bp.ps * bp.ps * 4);
+            bp.oVib = a.take(2 * (size_t)bp.ps * bp.ps * 4);
+            for (int q = 0; q < bp.nside * bp.nside; ++q) pl.ib_blk.push_back(make_int2((int)pl.bodies.size(), q));
+            pl.bodies.push_back(bp);
+        }
+        pl.sims.push_back(sp);
+    }
+    // fused work items: strips of <= T-8 columns, segments of seg rows
+    long strip_rows = 0;
+    for (int s = 0; s < n_sims; ++s) {
+        int W = pl.T - 2 * kHalo;
+        int ns = (sims[s].nx + W - 1) / W;
+        strip_rows += (long)ns * sims[s].ny;
+    }
+    int seg = o.seg;
+    if (seg <= 0) {
+        long target = 2048;
+        seg = (int)std::max(8L, std::min(64L, (strip_rows + target - 1) / target));
+        seg = (seg + 3) & ~3;
+    }
+    for (int s = 0; s < n_sims; ++s) {
+        int W = pl.T - 2 * kHalo;
+        int nx = sims[s].nx, ny = sims[s].ny;
+        int ns = (nx + W - 1) / W;
+        int ng = (ny + seg - 1) / seg;
+        for (int g = 0; g < ng; ++g) {
+            int y0 = (int)((long)g * ny / ng), y1 = (int)((long)(g + 1) * ny / ng);
+            for (int k = 0; k < ns; ++k) {
+                int x0 = (int)((long)k * nx / ns), x1 = (int)((long)(k + 1) * nx / ns);
+                pl.items.push_back(WorkItem{s, x0, y0, x1 - x0, y1 - y0, 0, 0, 0});
+            }
+        }
+    }
+    pl.oItems = a.take(sizeof(WorkItem) * pl.items.size());
+    pl.oIbBlk = a.take(sizeof(int2) * std::max<size_t>(1, pl.ib_blk.size()));
+    pl.oSiteBlk = a.take(sizeof(SiteBlock) * pl.site_blk.size());
+    pl.oT = a.take(sizeof(int));
+    pl.oStatus = a.take(sizeof(int));
+    pl.max_partial = 1024;
+    pl.oPartial = a.take(sizeof(double) * 3 * pl.max_partial);
+    pl.oOut = a.take(sizeof(double) * 16);
+    pl.oStage = a.take(10 * maxN * 4);
+    pl.bytes = a.off + 256;
+    return pl;
+}
+
+}  // namespace
+
+struct lb_handle {
+    int n_sims = 0;
+    Opt opt;
+    Plan plan;
+    std::vector<lb_sim_params> params;
+    std::vector<std::vector<lb_body_desc>> bdesc;
+    std::vector<SimDev> hs;
+    std::vector<BodyDev> hb;
+    std::vector<double> mass0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char *arena = nullptr;
+    SimDev *d_sims = nullptr;
+    BodyDev *d_bodies = nullptr;
+    WorkItem *d_items = nullptr;
+    int2 *d_ib = nullptr;
+    SiteBlock *d_site = nullptr;
+    int *d_t = nullptr;
+    int *d_status = nullptr;
+    double *d_partial = nullptr;
+    double *d_out = nullptr;
+    float *d_stage = nullptr;
+    int64_t t = 0;
+    int cur = 0;
+    int fused_grid = 0;
+    // graph replay
+    hipGraphExec_t gexec = nullptr;
+    int gsteps = 0;
+    // timing
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending_field, pending_ib;
+    double field_ms = 0, ib_ms = 0;
+    int64_t field_n = 0, ib_n = 0;
+    // watchdog
+    int *h_status = nullptr;   // pinned
+    hipEvent_t ev_wd = nullptr;
+    bool wd_pending = false;
+};
+
+namespace {
+
+int check_status(lb_handle *h) {
+    int st = 0;
+    HIPCHK(hipMemcpyAsync(&st, h->d_status, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (st & kStatusUnstable) return fail(LB_EUNSTABLE, "watchdog: non-finite or drifting mass");
+    if (st & kStatusPatch) return fail(LB_ERANGE, "a body outgrew its force patch (node motion too large)");
+    return LB_OK;
+}
+
+hipEvent_t pool_event(lb_handle *h) {
+    if (!h->ev_pool.empty()) {
+        hipEvent_t e = h->ev_pool.back();
+        h->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int drain_timing(lb_handle *h) {
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (auto &pr : h->pending_field) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+        h->field_ms += ms;
+        h->field_n += 1;
+        h->ev_pool.push_back(pr.first);
+        h->ev_pool.push_back(pr.second);
+    }
+    for (auto &pr : h->pending_ib) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+        h->ib_ms += ms;
+        h->ib_n += 1;
+        h->ev_pool.push_back(pr.first);
+        h->ev_pool.push_back(pr.second);
+    }
+    h->pending_field.clear();
+    h->pending_ib.clear();
+    return LB_OK;
+}
+
+// launch one step's kernels (field pass + node update); parity flips
+int launch_step(lb_handle *h, bool timed) {
+    const bool fp16 = h->opt.precision == 1;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (timed) {
+        a = pool_event(h);
+        b = pool_event(h);
+        if (!a || !b) return fail(LB_EDEVICE, "hipEventCreate failed");
+        HIPCHK(hipEventRecord(a, h->stream));
+    }
+    if (h->opt.kernel == 0) {
+        HIPCHK(launch_fused(h->plan.T, fp16, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
+                            (int)h->plan.items.size(), h->cur, h->d_t));
+    } else {
+        HIPCHK(launch_multipass(fp16, (int)h->plan.site_blk.size(), h->stream, h->d_sims, h->d_bodies, h->d_site,
+                                h->cur, h->d_t));
+    }
+    if (timed) {
+        HIPCHK(hipEventRecord(b, h->stream));
+        h->pending_field.emplace_back(a, b);
+    }
+    if (!h->plan.ib_blk.empty()) {
+        hipEvent_t c = nullptr, d = nullptr;
+        if (timed) {
+            c = pool_event(h);
+            d = pool_event(h);
+            if (!c || !d) return fail(LB_EDEVICE, "hipEventCreate failed");
+            HIPCHK(hipEventRecord(c, h->stream));
+        }
+        HIPCHK(launch_ib(true, (int)h->plan.ib_blk.size(), h->stream, h->d_sims, h->d_bodies, h->d_ib, h->cur, h->d_t,
+                         h->d_status));
+        if (timed) {
+            HIPCHK(hipEventRecord(d, h->stream));
+            h->pending_ib.emplace_back(c, d);
+        }
+    }
+    h->cur ^= 1;
+    h->t += 1;
+    if (timed && h->pending_field.size() >= 256) {
+        int rc = drain_timing(h);
+        if (rc) return rc;
+    }
+    return LB_OK;
+}
+
+int run_watchdog(lb_handle *h) {
+    const bool fp16 = h->opt.precision == 1;
+    for (int s = 0; s < h->n_sims; ++s) {
+        int nb = std::min(h->plan.max_partial, h->plan.sims[s].nblk);
+        HIPCHK(launch_sums(fp16, s, nb, h->stream, h->d_sims, h->cur, h->d_partial, h->d_out, h->mass0[s], h->d_status));
+    }
+    HIPCHK(hipMemcpyAsync(h->h_status, h->d_status, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipEventRecord(h->ev_wd, h->stream));
+    h->wd_pending = true;
+    return LB_OK;
+}
+
+int build_graph(lb_handle *h) {
+    hipGraph_t g = nullptr;
+    int cur0 = h->cur;
+    int64_t t0 = h->t;
+    HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    int rc = LB_OK;
+    for (int i = 0; i < h->opt.chunk && rc == LB_OK; ++i) rc = launch_step(h, false);
+    hipError_t e = hipStreamEndCapture(h->stream, &g);
+    h->cur = cur0;
+    h->t = t0;
+    if (rc != LB_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(LB_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    h->gsteps = h->opt.chunk;
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lb_last_error(void) { return g_err.c_str(); }
+
+int lb_query_arena_bytes(const lb_sim_params *sims, int32_t n_sims, const lb_options *opt, size_t *bytes) {
+    try {
+        if (!bytes) return fail(LB_EINVAL, "bytes is NULL");
+        Opt o = read_opt(opt);
+        int rc = validate(sims, n_sims, o);
+        if (rc) return rc;
+        *bytes = make_plan(sims, n_sims, o).bytes;
+        return LB_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(LB_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(LB_EINVAL, "unexpected host error");
+    }
+}
+
+static int create_impl(const lb_sim_params *sims, int n_sims, const lb_options *opt, void *arena, size_t arena_bytes,
+                       void *stream, lb_handle **out) {
+    if (!out) return fail(LB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!arena) return fail(LB_EINVAL, "device_arena is NULL");
+    if (((uintptr_t)arena) & 255) return fail(LB_EINVAL, "device_arena must be 256-byte aligned");
+    Opt o = read_opt(opt);
+    int rc = validate(sims, n_sims, o);
+    if (rc) return rc;
+    std::unique_ptr<lb_handle> h(new lb_handle());
+    h->n_sims = n_sims;
+    h->opt = o;
+    h->plan = make_plan(sims, n_sims, o);
+    if (arena_bytes < h->plan.bytes)
+        return fail(LB_ENOMEM, "arena too small: %zu bytes given, %zu needed", arena_bytes, h->plan.bytes);
+    h->arena = static_cast<char *>(arena);
+    if (stream) {
+        h->stream = static_cast<hipStream_t>(stream);
+    } else {
+        HIPCHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+        h->own_stream = true;
+    }
+    Arena A;
+    A.base = h->arena;
+    const Plan &pl = h->plan;
+    const bool fp16 = o.precision == 1;
+    const float scale = fp16 ? std::ldexp(1.0f, o.shift) : 1.0f;
+
+    // tables
+    std::vector<const Table *> tabs;
+    for (size_t i = 0; i < pl.clamps.size(); ++i) {
+        tabs.push_back(&stiffness_table(pl.clamps[i]));
+        HIPCHK(hipMemcpyAsync(A.ptr<float4>(pl.oTab[i]), tabs.back()->rows.data(), sizeof(float4) * kTab,
+                              hipMemcpyHostToDevice, h->stream));
+    }
+    h->d_sims = A.ptr<SimDev>(pl.oSims);
+    h->d_bodies = A.ptr<BodyDev>(pl.oBodies);
+    h->d_items = A.ptr<WorkItem>(pl.oItems);
+    h->d_ib = A.ptr<int2>(pl.oIbBlk);
+    h->d_site = A.ptr<SiteBlock>(pl.oSiteBlk);
+    h->d_t = A.ptr<int>(pl.oT);
+    h->d_status = A.ptr<int>(pl.oStatus);
+    h->d_partial = A.ptr<double>(pl.oPartial);
+    h->d_out = A.ptr<double>(pl.oOut);
+    h->d_stage = A.ptr<float>(pl.oStage);
+
+    // simulation descriptors and initial fields
+    std::vector<float> buf;
+    int body_index = 0;
+    for (int s = 0; s < n_sims; ++s) {
+        const lb_sim_params &p = sims[s];
+        const SimPlan &sp = pl.sims[s];
+        const size_t N = sp.N;
+        SimDev d{};
+        d.nx = p.nx;
+        d.ny = p.ny;
+        d.nb = p.n_bodies;
+        d.b0 = body_index;
+        d.omega = (float)(1.0 / p.tau);
+        d.guo = (float)(1.0 - 0.5 / p.tau);
+        d.inv_eta = (float)(1.0 / p.eta_p);
+        d.D = (float)p.D_p;
+        d.xi = (float)p.xi;
+        d.alpha = (float)p.alpha;
+        d.beta = (float)p.beta;
+        d.kappa = (float)p.kappa;
+        d.Gamma = (float)p.Gamma;
+        const double K1111 = p.Kx[0], K1122 = p.Kx[1], K2222 = p.Kx[2], K1212 = p.Kx[3];
+        d.cA = (float)(K1111 - 2 * K1122 - 4 * K1212 + K2222);
+        d.cB = (float)(K1111 - K2222);
+        d.S1 = (float)(3 * K1111 + 2 * K1122 + 4 * K1212 + 3 * K2222);
+        d.S2 = (float)(K1111 + 6 * K1122 - 4 * K1212 + K2222);
+        d.S3 = (float)(K1111 - 2 * K1122 + 4 * K1212 + K2222);
+        const Table &tb = *tabs[sp.tab];
+        d.smax = (float)(p.P_clamp * p.P_clamp);
+        d.inv_ds = (float)(kTab / (p.P_clamp * p.P_clamp));
+        d.A2max = (float)tb.A2max;
+        d.A4max = (float)tb.A4max;
+        d.scale = scale;
+        d.inv_scale = 1.0f / scale;
+        d.ericksen = p.ericksen ? 1 : 0;
+        d.tab = A.ptr<float4>(pl.oTab[sp.tab]);
+        d.h[0] = A.ptr<void>(sp.oH0);
+        d.h[1] = A.ptr<void>(sp.oH1);
+        d.sig[0] = A.ptr<float>(sp.oS0);
+        d.sig[1] = A.ptr<float>(sp.oS1);
+        d.P[0] = A.ptr<float>(sp.oP0);
+        d.P[1] = A.ptr<float>(sp.oP1);
+        d.sE = A.ptr<float>(sp.oSE);
+        d.v = o.kernel == 1 ? A.ptr<float>(sp.oV) : nullptr;
+        d.sp = o.kernel == 1 ? A.ptr<float>(sp.oSP) : nullptr;
+        h->hs.push_back(d);
+
+        // P and sigma
+        buf.assign(3 * N, 0.0f);
+        if (p.init_P)
+            for (size_t i = 0; i < 2 * N; ++i) buf[i] = (float)p.init_P[i];
+        HIPCHK(hipMemcpyAsync(d.P[0], buf.data(), 2 * N * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        std::fill(buf.begin(), buf.end(), 0.0f);
+        if (p.init_sigma)
+            for (size_t i = 0; i < 3 * N; ++i) buf[i] = (float)p.init_sigma[i];
+        HIPCHK(hipMemcpyAsync(d.sig[0], buf.data(), 3 * N * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        // populations: the stored array is post-collision of the previous step, pulled by the
+        // next step, so slot (x, y) of plane n holds h_n(x + c_n, y + c_n) - w_n
+        static const int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+        static const int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+        static const double WQ[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+        buf.assign(9 * N, 0.0f);
+        if (p.init_h) {
+            for (int n = 0; n < 9; ++n)
+                for (int y = 0; y < p.ny; ++y)
+                    for (int x = 0; x < p.nx; ++x) {
+                        int xs = (x + CX[n] + p.nx) % p.nx, ys = (y + CY[n] + p.ny) % p.ny;
+                        buf[(size_t)n * N + (size_t)y * p.nx + x] =
+                            (float)(p.init_h[(size_t)n * N + (size_t)ys * p.nx + xs] - WQ[n]);
+                    }
+        }
+        HIPCHK(hipMemcpyAsync(h->d_stage, buf.data(), 9 * N * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(launch_pack(fp16, h->stream, h->d_stage, d.h[0], 9 * N, scale));
+        HIPCHK(hipStreamSynchronize(h->stream));
+
+        // bodies
+        h->params.push_back(p);
+        h->bdesc.emplace_back(p.bodies, p.bodies + p.n_bodies);
+        for (int b = 0; b < p.n_bodies; ++b, ++body_index) {
+            const lb_body_desc &bd = p.bodies[b];
+            const BodyPlan &bp = pl.bodies[body_index];
+            BodyDev B{};
+            B.sim = s;
+            B.n = bd.n_nodes;
+            B.ps = bp.ps;
+            B.nside = bp.nside;
+            B.k = bd.k_spring;
+            B.eps = bd.eps_angle;
+            B.leq = bd.l_eq;
+            B.fx = bd.pull_fx;
+            B.fy = bd.pull_fy;
+            B.t_on = bd.pull_t_on;
+            B.t_off = bd.pull_t_off;
+            B.width = bd.pull_width;
+            B.R[0] = A.ptr<double>(bp.oR0);
+            B.R[1] = A.ptr<double>(bp.oR1);
+            B.fnode = A.ptr<double>(bp.oF);
+            B.origin = A.ptr<int>(bp.oOrigin);
+            B.fib = A.ptr<float>(bp.oFib);
+            B.vib = A.ptr<float>(bp.oVib);
+            std::vector<double> R(2 * (size_t)bd.n_nodes);
+            for (int a = 0; a < bd.n_nodes; ++a) {
+                if (bd.nodes) {
+                    R[2 * a] = bd.nodes[2 * a];
+                    R[2 * a + 1] = bd.nodes[2 * a + 1];
+                } else {
+                    double ang = 2.0 * M_PI * a / bd.n_nodes;
+                    R[2 * a] = bd.cx + bd.radius * std::cos(ang);
+                    R[2 * a + 1] = bd.cy + bd.radius * std::sin(ang);
+                }
+            }
+            HIPCHK(hipMemcpyAsync(B.R[0], R.data(), R.size() * 8, hipMemcpyHostToDevice, h->stream));
+            HIPCHK(hipMemcpyAsync(B.R[1], R.data(), R.size() * 8, hipMemcpyHostToDevice, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+            h->hb.push_back(B);
+        }
+    }
+    HIPCHK(hipMemcpyAsync(h->d_sims, h->hs.data(), sizeof(SimDev) * n_sims, hipMemcpyHostToDevice, h->stream));
+    if (!h->hb.empty())
+        HIPCHK(hipMemcpyAsync(h->d_bodies, h->hb.data(), sizeof(BodyDev) * h->hb.size(), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->d_items, pl.items.data(), sizeof(WorkItem) * pl.items.size(), hipMemcpyHostToDevice, h->stream));
+    if (!pl.ib_blk.empty())
+        HIPCHK(hipMemcpyAsync(h->d_ib, pl.ib_blk.data(), sizeof(int2) * pl.ib_blk.size(), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->d_site, pl.site_blk.data(), sizeof(SiteBlock) * pl.site_blk.size(), hipMemcpyHostToDevice,
+                          h->stream));
+    int zero[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(h->d_t, zero, sizeof(int), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->d_status, zero, sizeof(int), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->fused_grid = (int)pl.items.size();
+
+    // initial body forces spread onto their patches
+    if (!pl.ib_blk.empty())
+        HIPCHK(launch_ib(false, (int)pl.ib_blk.size(), h->stream, h->d_sims, h->d_bodies, h->d_ib, 0, h->d_t, h->d_status));
+    // reference mass for the watchdog
+    for (int s = 0; s < n_sims; ++s) {
+        int nb = std::min(pl.max_partial, pl.sims[s].nblk);
+        HIPCHK(launch_sums(fp16, s, nb, h->stream, h->d_sims, 0, h->d_partial, h->d_out, 0.0, h->d_status));
+        double m[3];
+        HIPCHK(hipMemcpyAsync(m, h->d_out, sizeof m, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        h->mass0.push_back(m[0]);
+    }
+    HIPCHK(hipHostMalloc((void **)&h->h_status, sizeof(int), hipHostMallocDefault));
+    *h->h_status = 0;
+    HIPCHK(hipEventCreateWithFlags(&h->ev_wd, hipEventDisableTiming));
+    rc = check_status(h.get());
+    if (rc) return rc;
+    *out = h.release();
+    return LB_OK;
+}
+
+int lb_create(const lb_sim_params *sims, int32_t n_sims, const lb_options *opt, void *device_arena, size_t arena_bytes,
+              void *hip_stream, lb_handle **out) {
+    try {
+        return create_impl(sims, n_sims, opt, device_arena, arena_bytes, hip_stream, out);
+    } catch (const std::bad_alloc &) {
+        return fail(LB_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(LB_EINVAL, "unexpected host error");
+    }
+}
+
+int lb_step(lb_handle *h, int32_t n_steps) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (n_steps < 0) return fail(LB_EINVAL, "n_steps must be >= 0");
+    try {
+        if (h->wd_pending && hipEventQuery(h->ev_wd) == hipSuccess) {
+            h->wd_pending = false;
+            if (*h->h_status & kStatusUnstable) return fail(LB_EUNSTABLE, "watchdog: non-finite or drifting mass");
+            if (*h->h_status & kStatusPatch) return fail(LB_ERANGE, "a body outgrew its force patch");
+        }
+        const bool use_graph = h->opt.chunk > 0 && !h->opt.timing;
+        int done = 0;
+        while (done < n_steps) {
+            int rc;
+            int left = n_steps - done;
+            const int wd = h->opt.watchdog;
+            int until_wd = wd > 0 ? (int)(wd - (h->t % wd)) : left;
+            if (use_graph && h->cur == 0 && left >= h->opt.chunk && until_wd >= h->opt.chunk) {
+                if (!h->gexec) {
+                    rc = build_graph(h);
+                    if (rc) return rc;
+                }
+                HIPCHK(hipGraphLaunch(h->gexec, h->stream));
+                h->t += h->gsteps;
+                done += h->gsteps;
+            } else {
+                rc = launch_step(h, h->opt.timing != 0);
+                if (rc) return rc;
+                done += 1;
+            }
+            if (wd > 0 && h->t % wd == 0) {
+                rc = run_watchdog(h);
+                if (rc) return rc;
+            }
+        }
+        HIPCHK(hipGetLastError());
+        return LB_OK;
+    } catch (...) {
+        return fail(LB_EINVAL, "unexpected host error");
+    }
+}
+
+int lb_sync(lb_handle *h) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return check_status(h);
+}
+
+int lb_time(lb_handle *h, int64_t *t) {
+    if (!h || !t) return fail(LB_EINVAL, "NULL argument");
+    *t = h->t;
+    return LB_OK;
+}
+
+int lb_read_fields(lb_handle *h, int32_t sim, uint32_t mask, double *out, size_t n_out) {
+    if (!h || !out) return fail(LB_EINVAL, "NULL argument");
+    if (sim < 0 || sim >= h->n_sims) return fail(LB_ERANGE, "sim index out of range");
+    if (mask & ~LB_F_ALL) return fail(LB_EINVAL, "unknown field bits");
+    try {
+        int rc = check_status(h);
+        if (rc) return rc;
+        const SimPlan &sp = h->plan.sims[sim];
+        const size_t N = sp.N;
+        int nplanes = 0;
+        for (int b = 0; b < 10; ++b) nplanes += (mask >> b) & 1;
+        size_t nodes = 0;
+        if (mask & LB_F_NODES)
+            for (const auto &bd : h->bdesc[sim]) nodes += 2 * (size_t)bd.n_nodes;
+        if (n_out < nplanes * N + nodes) return fail(LB_ERANGE, "output buffer too small");
+        if (nplanes) {
+            HIPCHK(launch_readout(h->opt.precision == 1, sp.nblk, sp.blk0, h->stream, h->d_sims, h->d_bodies, h->d_site,
+                                  h->cur, h->d_stage));
+            std::vector<float> st(10 * N);
+            HIPCHK(hipMemcpyAsync(st.data(), h->d_stage, 10 * N * 4, hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+            size_t o = 0;
+            for (int b = 0; b < 10; ++b) {
+                if (!((mask >> b) & 1)) continue;
+                const float *src = st.data() + (size_t)b * N;
+                if (b == 0)
+                    for (size_t i = 0; i < N; ++i) out[o + i] = 1.0 + (double)src[i];
+                else
+                    for (size_t i = 0; i < N; ++i) out[o + i] = (double)src[i];
+                o += N;
+            }
+        }
+        if (mask & LB_F_NODES) {
+            size_t o = nplanes * N;
+            for (int b = 0; b < h->params[sim].n_bodies; ++b) {
+                const BodyDev &B = h->hb[h->hs[sim].b0 + b];
+                HIPCHK(hipMemcpyAsync(out + o, B.R[h->cur], 16 * (size_t)B.n, hipMemcpyDeviceToHost, h->stream));
+                o += 2 * (size_t)B.n;
+            }
+            HIPCHK(hipStreamSynchronize(h->stream));
+        }
+        return check_status(h);
+    } catch (const std::bad_alloc &) {
+        return fail(LB_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(LB_EINVAL, "unexpected host error");
+    }
+}
+
+int lb_body_force(lb_handle *h, int32_t sim, int32_t body, double out[8]) {
+    if (!h || !out) return fail(LB_EINVAL, "NULL argument");
+    if (sim < 0 || sim >= h->n_sims) return fail(LB_ERANGE, "sim index out of range");
+    if (body < 0 || body >= h->params[sim].n_bodies) return fail(LB_ERANGE, "body index out of range");
+    int rc = check_status(h);
+    if (rc) return rc;
+    const int bi = h->hs[sim].b0 + body;
+    HIPCHK(launch_body_force(h->stream, h->d_sims, h->d_bodies, bi, h->cur, h->d_out));
+    double r[6];
+    HIPCHK(hipMemcpyAsync(r, h->d_out, sizeof r, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const BodyDev &B = h->hb[bi];
+    double pf = 1.0;
+    if (B.width > 0.0) {
+        double t = (double)h->t;
+        pf = 1.0 / (1.0 + std::exp(-(t - B.t_on) / B.width)) - 1.0 / (1.0 + std::exp(-(t - B.t_off) / B.width));
+    }
+    out[0] = r[0];
+    out[1] = r[1];
+    out[2] = pf * B.fx;
+    out[3] = pf * B.fy;
+    out[4] = r[2];
+    out[5] = r[3];
+    out[6] = r[4];
+    out[7] = r[5];
+    return check_status(h);
+}
+
+int lb_conservation(lb_handle *h, int32_t sim, double out[3]) {
+    if (!h || !out) return fail(LB_EINVAL, "NULL argument");
+    if (sim < 0 || sim >= h->n_sims) return fail(LB_ERANGE, "sim index out of range");
+    int rc = check_status(h);
+    if (rc) return rc;
+    int nb = std::min(h->plan.max_partial, h->plan.sims[sim].nblk);
+    HIPCHK(launch_sums(h->opt.precision == 1, sim, nb, h->stream, h->d_sims, h->cur, h->d_partial, h->d_out, 0.0,
+                       h->d_status));
+    HIPCHK(hipMemcpyAsync(out, h->d_out, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+int lb_timing(lb_handle *h, double *field_ms, int64_t *field_n, double *ib_ms, int64_t *ib_n, int32_t reset) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    int rc = drain_timing(h);
+    if (rc) return rc;
+    if (field_ms) *field_ms = h->field_ms;
+    if (field_n) *field_n = h->field_n;
+    if (ib_ms) *ib_ms = h->ib_ms;
+    if (ib_n) *ib_n = h->ib_n;
+    if (reset) {
+        h->field_ms = h->ib_ms = 0;
+        h->field_n = h->ib_n = 0;
+    }
+    return LB_OK;
+}
+
+int lb_destroy(lb_handle *h) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    (void)hipStreamSynchronize(h->stream);
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    for (auto &pr : h->pending_field) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    for (auto &pr : h->pending_ib) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    for (auto e : h->ev_pool) (void)hipEventDestroy(e);
+    if (h->ev_wd) (void)hipEventDestroy(h->ev_wd);
+    if (h->h_status) (void)hipHostFree(h->h_status);
+    if (h->own_stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+    return LB_OK;
+}
+
+}  // extern "C"

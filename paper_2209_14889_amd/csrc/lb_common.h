@@ -1,0 +1,62 @@
+// Shared host/device layout of liblb (MI355X, gfx950).  Plain structs of device pointers and
+// coefficients; the host builds them once in lb_create and kernels read them from the arena.
+#pragma once
+#include <stdint.h>
+
+namespace lbk {
+
+constexpr int kMaxNodes = 1024;     // nodes per body
+constexpr int kMaxBodies = 64;      // bodies per simulation
+constexpr int kPatchTile = 16;      // immersed-boundary gather block: 16 x 16 patch sites
+constexpr int kTab = 4096;          // stiffness-table intervals over s = |P|^2 in [0, P_clamp^2]
+constexpr int kHalo = 4;            // fused kernel: polarization halo depth (stress and h use 3)
+constexpr int kDefaultShift = 10;   // FP16 storage: offsets scaled by 2^10
+
+// status bits raised by kernels, read by the host at synchronising calls
+constexpr int kStatusPatch = 1;     // a body outgrew its force/velocity patch
+constexpr int kStatusUnstable = 2;  // watchdog: non-finite or drifting mass
+
+struct SimDev {
+    int nx, ny;
+    int nb, b0;                     // bodies of this simulation: count, first index
+    float omega, guo;               // 1/tau and 1 - 1/(2 tau)  (BGK, Guo forcing)
+    float inv_eta, D;               // 1/eta_p, D_p
+    float xi, alpha, beta, kappa, Gamma;
+    float cA, cB;                   // K1111-2K1122-4K1212+K2222, K1111-K2222
+    float S1, S2, S3;               // isotropic parts: 3K1111+2K1122+4K1212+3K2222,
+                                    // K1111+6K1122-4K1212+K2222, K1111-2K1122+4K1212+K2222
+    float smax, inv_ds;             // table range P_clamp^2 and intervals per unit s
+    float A2max, A4max;             // a2/s and a4/s^2 at smax
+    float inv_scale, scale;         // FP16 storage scale 2^-S and 2^S (1 for FP32)
+    int ericksen;
+    int pad0;
+    const float4 *tab;              // per interval: (A2, dA2, A4, dA4), A2 = a2/s, A4 = a4/s^2
+    void *h[2];                     // post-collision population offsets, 9 planes (float or half)
+    float *sig[2];                  // polymer stress planes sxx, syy, sxy
+    float *P[2];                    // polarization planes Px, Py
+    float *sE;                      // multi-pass scratch: Ericksen stress xx, xy, yx, yy
+    float *v;                       // multi-pass scratch: velocity
+    float *sp;                      // multi-pass scratch: predicted sigma (3) and P (2)
+};
+
+struct BodyDev {
+    int sim, n, ps, nside;          // owning sim, nodes, patch side, gather blocks per side
+    double k, eps, leq, fx, fy, t_on, t_off, width;
+    double *R[2];                   // node positions by step parity, interleaved x, y
+    double *fnode;                  // node forces at the current time (2n)
+    int *origin;                    // patch origin by step parity: [parity][2]
+    float *fib;                     // spread force patch: 2 planes ps*ps
+    float *vib;                     // fluid velocity patch: 2 planes ps*ps
+};
+
+// fused kernel work item: columns [x0, x0+w), rows [y0, y0+l) of one simulation
+struct WorkItem {
+    int sim, x0, y0, w, l, pad0, pad1, pad2;
+};
+
+// multi-pass kernels: one 256-site block of one simulation
+struct SiteBlock {
+    int sim, start;
+};
+
+}  // namespace lbk

@@ -1,0 +1,218 @@
+// Device-side arithmetic of one lattice site, shared by the fused and multi-pass kernels.
+//
+// Populations are stored as offsets from the rest weights, d_n = h_n - w_n (FP32 arithmetic;
+// FP32 or FP16-times-2^S storage).  Every right-hand side takes time-t inputs (Fig. 2 caption).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include "lb_common.h"
+
+namespace lbk {
+
+// D2Q9: rest, +x, +y, -x, -y, (+,+), (-,+), (-,-), (+,-)
+__device__ constexpr int kCX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int kCY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ constexpr float kW[9] = {4.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f,
+                                    1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+// ---- population storage -----------------------------------------------------------------
+template <typename HT> struct Pop;
+template <> struct Pop<float> {
+    static __device__ __forceinline__ float load(const float *p, size_t i, float) { return p[i]; }
+    static __device__ __forceinline__ void store(float *p, size_t i, float v, float) { p[i] = v; }
+};
+template <> struct Pop<__half> {
+    static __device__ __forceinline__ float load(const __half *p, size_t i, float inv_scale) {
+        return __half2float(p[i]) * inv_scale;
+    }
+    static __device__ __forceinline__ void store(__half *p, size_t i, float v, float scale) {
+        p[i] = __float2half_rn(v * scale);
+    }
+};
+
+// ---- BGK collision with Guo forcing (eqBGK, Sec. II B force coupling) --------------------
+// In: pre-collision offsets d[9], force F.  Out: post-collision offsets in d, and the
+// force-corrected velocity u = (sum c h + F/2)/rho, drho = rho - 1.
+__device__ __forceinline__ void collide(float d[9], float Fx, float Fy, float omega, float guo,
+                                        float &drho, float &ux, float &uy) {
+    float s0 = (d[0] + d[1]) + (d[2] + d[3]);
+    float s1 = (d[4] + d[5]) + (d[6] + d[7]);
+    drho = (s0 + s1) + d[8];
+    float jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]) + 0.5f * Fx;
+    float jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]) + 0.5f * Fy;
+    float rho = 1.0f + drho;
+    float ir = 1.0f / rho;
+    ux = jx * ir;
+    uy = jy * ir;
+    float uu15 = 1.5f * (ux * ux + uy * uy);
+    float uF = ux * Fx + uy * Fy;
+#pragma unroll
+    for (int n = 0; n < 9; ++n) {
+        float cu = kCX[n] * ux + kCY[n] * uy;
+        float cF = kCX[n] * Fx + kCY[n] * Fy;
+        // equilibrium offset: w (rho (1 + 3cu + 4.5cu^2 - 1.5u^2) - 1)
+        float deq = kW[n] * (drho + rho * (cu * (3.0f + 4.5f * cu) - uu15));
+        float src = guo * kW[n] * (3.0f * (cF - uF) + 9.0f * cu * cF);
+        d[n] = d[n] + omega * (deq - d[n]) + src;
+    }
+}
+
+// ---- stiffness C~(P) (App. B) via tables of a2/s and a4/s^2 in s = |P|^2 ------------------
+// a2 cos(2 th) = A2 (Px^2 - Py^2), a2 sin(2 th) = A2 2 Px Py, and the same for a4 with the
+// squares of those harmonics, so no angle and no division by |P| are needed.
+struct Stiff {
+    float X1, X2, Y1, Y2;   // a4 c4 cA, a2 c2 cB, a4 s4 cA, a2 s2 cB
+};
+
+__device__ __forceinline__ Stiff stiffness(const SimDev &S, float Px, float Py) {
+    float sx = Px * Px, sy = Py * Py;
+    float s = sx + sy;
+    float A2, A4;
+    if (s < S.smax) {
+        float u = s * S.inv_ds;
+        int i = min((int)u, kTab - 1);
+        float fr = u - (float)i;
+        float4 t = S.tab[i];
+        A2 = fmaf(fr, t.y, t.x);
+        A4 = fmaf(fr, t.w, t.z);
+    } else {
+        float r = S.smax / s;
+        A2 = S.A2max * r;
+        A4 = S.A4max * r * r;
+    }
+    float dd = sx - sy, ee = 2.0f * Px * Py;
+    Stiff k;
+    k.X1 = A4 * (dd * dd - ee * ee) * S.cA;
+    k.Y1 = A4 * (2.0f * dd * ee) * S.cA;
+    k.X2 = A2 * dd * S.cB;
+    k.Y2 = A2 * ee * S.cB;
+    return k;
+}
+
+// y = C~ x on plain components (xx, yy, xy)
+__device__ __forceinline__ void stiff_apply(const SimDev &S, const Stiff &k, float a, float b, float c,
+                                            float &o0, float &o1, float &o2) {
+    float C11 = 0.125f * (k.X1 + S.S1 + 4.0f * k.X2);
+    float C22 = C11 - k.X2;
+    float C12 = 0.125f * (S.S2 - k.X1);
+    float C33 = 0.25f * (S.S3 - k.X1);
+    float C13 = 0.25f * (k.Y1 + 2.0f * k.Y2);
+    float C23 = 0.25f * (2.0f * k.Y2 - k.Y1);
+    o0 = C11 * a + C12 * b + C13 * c;
+    o1 = C12 * a + C22 * b + C23 * c;
+    o2 = 0.5f * (C13 * a + C23 * b) + C33 * c;
+}
+
+// velocity gradient pieces at a site from central differences
+struct Grad {
+    float psi0, psi1, psi2, om;   // Psi_xx, Psi_yy, Psi_xy, Omega_xy
+};
+
+__device__ __forceinline__ Grad grad_v(float vxe, float vxw, float vxn, float vxs,
+                                       float vye, float vyw, float vyn, float vys) {
+    float Gxx = 0.5f * (vxe - vxw), Gxy = 0.5f * (vye - vyw);
+    float Gyx = 0.5f * (vxn - vxs), Gyy = 0.5f * (vyn - vys);
+    Grad g;
+    g.psi0 = Gxx;
+    g.psi1 = Gyy;
+    g.psi2 = 0.5f * (Gxy + Gyx);
+    g.om = 0.5f * (Gxy - Gyx);
+    return g;
+}
+
+// right-hand side of eqStiffCons (corotational derivative) for one component set:
+// -(v.grad)X - (Omega X - X Omega) + C~(Psi - X/eta_p) + D_p lap X.
+// X[c] centre, e/w/n/s neighbours of each component.
+__device__ __forceinline__ void rhs_sigma(const SimDev &S, const Stiff &k, const Grad &g, float ux, float uy,
+                                          const float X[3], const float Xe[3], const float Xw[3],
+                                          const float Xn[3], const float Xs[3], float R[3]) {
+    float a = g.psi0 - S.inv_eta * X[0];
+    float b = g.psi1 - S.inv_eta * X[1];
+    float c = g.psi2 - S.inv_eta * X[2];
+    float C0, C1, C2;
+    stiff_apply(S, k, a, b, c, C0, C1, C2);
+    float J0 = 2.0f * g.om * X[2];
+    float J2 = g.om * (X[1] - X[0]);
+    float Cv[3] = {C0, C1, C2};
+    float Jv[3] = {J0, -J0, J2};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        float adv = ux * (0.5f * (Xe[q] - Xw[q])) + uy * (0.5f * (Xn[q] - Xs[q]));
+        float lap = ((Xe[q] + Xw[q]) + (Xn[q] + Xs[q])) - 4.0f * X[q];
+        R[q] = Cv[q] - Jv[q] - adv + S.D * lap;
+    }
+}
+
+// right-hand side of eqBE: -(v.grad)Y - Omega Y + xi Psi Y - Gamma h(Y),
+// h = (alpha + beta |Y|^2) Y - kappa lap Y
+__device__ __forceinline__ void rhs_P(const SimDev &S, const Grad &g, float ux, float uy,
+                                      const float Y[2], const float Ye[2], const float Yw[2],
+                                      const float Yn[2], const float Ys[2], float R[2]) {
+    float a = S.alpha + S.beta * (Y[0] * Y[0] + Y[1] * Y[1]);
+    float lap0 = ((Ye[0] + Yw[0]) + (Yn[0] + Ys[0])) - 4.0f * Y[0];
+    float lap1 = ((Ye[1] + Yw[1]) + (Yn[1] + Ys[1])) - 4.0f * Y[1];
+    float h0 = a * Y[0] - S.kappa * lap0;
+    float h1 = a * Y[1] - S.kappa * lap1;
+    float adv0 = ux * (0.5f * (Ye[0] - Yw[0])) + uy * (0.5f * (Yn[0] - Ys[0]));
+    float adv1 = ux * (0.5f * (Ye[1] - Yw[1])) + uy * (0.5f * (Yn[1] - Ys[1]));
+    R[0] = -adv0 - g.om * Y[1] + S.xi * (g.psi0 * Y[0] + g.psi2 * Y[1]) - S.Gamma * h0;
+    R[1] = -adv1 + g.om * Y[0] + S.xi * (g.psi2 * Y[0] + g.psi1 * Y[1]) - S.Gamma * h1;
+}
+
+// Ericksen stress at a site (Sec. II C 1, with kappa on the gradient term):
+// out = (xx, xy, yx, yy)
+__device__ __forceinline__ void ericksen(const SimDev &S, const float P[2], const float Pe[2], const float Pw[2],
+                                         const float Pn[2], const float Ps[2], float E[4]) {
+    float a = S.alpha + S.beta * (P[0] * P[0] + P[1] * P[1]);
+    float lap0 = ((Pe[0] + Pw[0]) + (Pn[0] + Ps[0])) - 4.0f * P[0];
+    float lap1 = ((Pe[1] + Pw[1]) + (Pn[1] + Ps[1])) - 4.0f * P[1];
+    float hx = a * P[0] - S.kappa * lap0;
+    float hy = a * P[1] - S.kappa * lap1;
+    float dxPx = 0.5f * (Pe[0] - Pw[0]), dyPx = 0.5f * (Pn[0] - Ps[0]);
+    float dxPy = 0.5f * (Pe[1] - Pw[1]), dyPy = 0.5f * (Pn[1] - Ps[1]);
+    float anti = -0.5f * (P[0] * hy - hx * P[1]);
+    float sym = 0.5f * S.xi * (P[0] * hy + hx * P[1]);
+    float gxy = S.kappa * (dxPx * dyPx + dxPy * dyPy);
+    E[0] = S.xi * P[0] * hx - S.kappa * (dxPx * dxPx + dxPy * dxPy);
+    E[1] = anti + sym - gxy;
+    E[2] = -anti + sym - gxy;
+    E[3] = S.xi * P[1] * hy - S.kappa * (dyPx * dyPx + dyPy * dyPy);
+}
+
+// immersed-boundary force at lattice site (x, y) from the bodies' spread-force patches
+__device__ __forceinline__ void ib_force(const SimDev &S, const BodyDev *bodies, int parity, int x, int y,
+                                         float &Fx, float &Fy) {
+    for (int b = 0; b < S.nb; ++b) {
+        const BodyDev &B = bodies[S.b0 + b];
+        int ox = B.origin[2 * parity], oy = B.origin[2 * parity + 1];
+        int px = wrapi(x - ox, S.nx), py = wrapi(y - oy, S.ny);
+        if (px < B.ps && py < B.ps) {
+            size_t i = (size_t)py * B.ps + px;
+            Fx += B.fib[i];
+            Fy += B.fib[(size_t)B.ps * B.ps + i];
+        }
+    }
+}
+
+// store the fluid velocity into the bodies' velocity patches (read by the node update)
+__device__ __forceinline__ void ib_store_v(const SimDev &S, const BodyDev *bodies, int parity, int x, int y,
+                                           float ux, float uy) {
+    for (int b = 0; b < S.nb; ++b) {
+        const BodyDev &B = bodies[S.b0 + b];
+        int ox = B.origin[2 * parity], oy = B.origin[2 * parity + 1];
+        int px = wrapi(x - ox, S.nx), py = wrapi(y - oy, S.ny);
+        if (px < B.ps && py < B.ps) {
+            size_t i = (size_t)py * B.ps + px;
+            B.vib[i] = ux;
+            B.vib[(size_t)B.ps * B.ps + i] = uy;
+        }
+    }
+}
+
+}  // namespace lbk

@@ -1,0 +1,862 @@
+// HIP kernels of liblb for gfx950 (MI355X).
+//
+//   k_ib          immersed-body node update (App. A), node forces and force spreading
+//   k_fused       one pass per step over every lattice site: forces, BGK + Guo collide with pull
+//                 streaming, velocity gradient, stiffness, Heun stress and polarization
+//   k_mp_*        the same step as four simple site-parallel kernels (debug / reference path)
+//   k_readout     observables at the current time
+//   k_sums / k_sums_final, k_body_force   FP64 reductions
+//
+// The fused kernel walks a strip of columns down its rows like a pipeline.  Iteration j loads the
+// polarization of row f = y0 - 4 + j and the stress of row f-1, forms the Ericksen stress at row
+// f-1, collides row f-2, predicts row f-3 and corrects row f-4.  Every stage only needs rows that
+// earlier stages or earlier iterations produced, so each value is computed once per column and
+// row exchanges go through small LDS ring buffers.
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include "lb_device.h"
+#include "lb_launch.h"
+
+namespace lbk {
+
+// ------------------------------------------------------------------------------------------------
+// immersed boundary
+// ------------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ double phi_d(double r) {
+    double a = fabs(r);
+    return a < 2.0 ? 0.25 * (1.0 + cos(0.5 * M_PI * r)) : 0.0;
+}
+
+__device__ __forceinline__ double pull_factor(const BodyDev &B, double t) {
+    if (B.width <= 0.0) return 1.0;
+    return 1.0 / (1.0 + exp(-(t - B.t_on) / B.width)) - 1.0 / (1.0 + exp(-(t - B.t_off) / B.width));
+}
+
+// v at point R from the body's velocity patch (origin ox, oy); flags reads outside the patch
+__device__ __forceinline__ void interp_patch(const BodyDev &B, int ox, int oy, double Rx, double Ry,
+                                             double &vx, double &vy, bool &bad) {
+    int ix = (int)floor(Rx) - 1, iy = (int)floor(Ry) - 1;
+    const size_t pp = (size_t)B.ps * B.ps;
+    vx = 0.0;
+    vy = 0.0;
+    for (int j = 0; j < 4; ++j) {
+        int Y = iy + j;
+        int py = Y - oy;
+        double wy = phi_d(Ry - Y);
+        for (int i = 0; i < 4; ++i) {
+            int X = ix + i;
+            int px = X - ox;
+            double w = phi_d(Rx - X) * wy;
+            if (px < 0 || py < 0 || px >= B.ps || py >= B.ps) {
+                bad = true;
+                continue;
+            }
+            size_t q = (size_t)py * B.ps + px;
+            vx += w * (double)B.vib[q];
+            vy += w * (double)B.vib[pp + q];
+        }
+    }
+}
+
+// derivative of cos(gamma_j) with respect to e1 = R_{j-1} - R_j (d1) and e2 = R_{j+1} - R_j (d2)
+__device__ __forceinline__ void angle_grads(const double2 *R, int n, int j, double2 &d1, double2 &d2) {
+    int jm = j == 0 ? n - 1 : j - 1, jp = j == n - 1 ? 0 : j + 1;
+    double e1x = R[jm].x - R[j].x, e1y = R[jm].y - R[j].y;
+    double e2x = R[jp].x - R[j].x, e2y = R[jp].y - R[j].y;
+    double n1 = sqrt(e1x * e1x + e1y * e1y), n2 = sqrt(e2x * e2x + e2y * e2y);
+    double in12 = 1.0 / (n1 * n2);
+    double cg = (e1x * e2x + e1y * e2y) * in12;
+    d1.x = e2x * in12 - cg * e1x / (n1 * n1);
+    d1.y = e2y * in12 - cg * e1y / (n1 * n1);
+    d2.x = e1x * in12 - cg * e2x / (n2 * n2);
+    d2.y = e1y * in12 - cg * e2y / (n2 * n2);
+}
+
+// spring force k (l - l_eq) d/l on node i from the spring to node j (d = R_j - R_i)
+__device__ __forceinline__ double2 spring_pull(const double2 *R, int i, int j, double k, double leq) {
+    double dx = R[j].x - R[i].x, dy = R[j].y - R[i].y;
+    double l = sqrt(dx * dx + dy * dy);
+    double c = k * (l - leq) / l;
+    return make_double2(c * dx, c * dy);
+}
+
+// -dU/dR_a for U = sum springs + sum bending (eqConst), plus the pull share
+__device__ __forceinline__ double2 node_force(const BodyDev &B, const double2 *R, int a, double pf) {
+    const int n = B.n;
+    int am = a == 0 ? n - 1 : a - 1, ap = a == n - 1 ? 0 : a + 1;
+    double2 s1 = spring_pull(R, a, ap, B.k, B.leq);
+    double2 s0 = spring_pull(R, a, am, B.k, B.leq);
+    double2 d1a, d2a, d1m, d2m, d1p, d2p;
+    angle_grads(R, n, a, d1a, d2a);
+    angle_grads(R, n, am, d1m, d2m);
+    angle_grads(R, n, ap, d1p, d2p);
+    double fx = s1.x + s0.x + B.eps * ((d1a.x + d2a.x) - d2m.x - d1p.x) + pf * B.fx / n;
+    double fy = s1.y + s0.y + B.eps * ((d1a.y + d2a.y) - d2m.y - d1p.y) + pf * B.fy / n;
+    return make_double2(fx, fy);
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// One block per (body, 16x16 patch tile).  ADVANCE: move the nodes from R(t) to R(t+1) by Heun
+// with the velocity patch written during step t, then compute the forces at the new positions
+// with the pull at time *d_t; otherwise use R[cur] as it is.  Every block of a body repeats the
+// (cheap) node work; block 0 of the body stores nodes, forces and the new patch origin.
+template <bool ADVANCE>
+__global__ __launch_bounds__(256) void k_ib(const SimDev *__restrict__ sims, BodyDev *__restrict__ bodies,
+                                            const int2 *__restrict__ blk, int cur, const int *__restrict__ d_t,
+                                            int *__restrict__ d_status) {
+    __shared__ double2 sR[kMaxNodes];
+    __shared__ double2 sF[kMaxNodes];
+    __shared__ int sList[kMaxNodes];
+    __shared__ double sRed[4][4];
+    __shared__ int sCnt[4];
+    __shared__ int sTot;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int2 bt = blk[blockIdx.x];
+    const BodyDev &B = bodies[bt.x];
+    const SimDev &S = sims[B.sim];
+    const int n = B.n;
+    const int dst = ADVANCE ? (cur ^ 1) : cur;
+    bool bad = false;
+
+    // 1. positions at the new time
+    const double2 *Rc = reinterpret_cast<const double2 *>(B.R[cur]);
+    int ox = 0, oy = 0;
+    if (ADVANCE) {
+        ox = B.origin[2 * cur];
+        oy = B.origin[2 * cur + 1];
+    }
+    for (int a = tid; a < n; a += 256) {
+        double2 R = Rc[a];
+        if (ADVANCE) {
+            double v1x, v1y, v2x, v2y;
+            interp_patch(B, ox, oy, R.x, R.y, v1x, v1y, bad);
+            interp_patch(B, ox, oy, R.x + v1x, R.y + v1y, v2x, v2y, bad);
+            R.x += 0.5 * (v1x + v2x);
+            R.y += 0.5 * (v1y + v2y);
+        }
+        sR[a] = R;
+    }
+    __syncthreads();
+
+    // 2. node forces and the bounding box of the nodes
+    const double pf = pull_factor(B, (double)d_t[0]);
+    double mnx = 1e300, mny = 1e300, mxx = -1e300, mxy = -1e300;
+    for (int a = tid; a < n; a += 256) {
+        sF[a] = node_force(B, sR, a, pf);
+        mnx = fmin(mnx, sR[a].x);
+        mny = fmin(mny, sR[a].y);
+        mxx = fmax(mxx, sR[a].x);
+        mxy = fmax(mxy, sR[a].y);
+    }
+    mnx = wave_min(mnx);
+    mny = wave_min(mny);
+    mxx = wave_max(mxx);
+    mxy = wave_max(mxy);
+    if (lane == 0) {
+        sRed[wv][0] = mnx;
+        sRed[wv][1] = mny;
+        sRed[wv][2] = mxx;
+        sRed[wv][3] = mxy;
+    }
+    __syncthreads();
+    mnx = fmin(fmin(sRed[0][0], sRed[1][0]), fmin(sRed[2][0], sRed[3][0]));
+    mny = fmin(fmin(sRed[0][1], sRed[1][1]), fmin(sRed[2][1], sRed[3][1]));
+    mxx = fmax(fmax(sRed[0][2], sRed[1][2]), fmax(sRed[2][2], sRed[3][2]));
+    mxy = fmax(fmax(sRed[0][3], sRed[1][3]), fmax(sRed[2][3], sRed[3][3]));
+    // patch: 3 sites of margin below the lowest node covers the kernel support (2) plus one
+    // site of node motion; the same margin above is checked against the patch side
+    const int nox = (int)floor(mnx) - 3, noy = (int)floor(mny) - 3;
+    if ((int)floor(mxx) + 3 - nox >= B.ps || (int)floor(mxy) + 3 - noy >= B.ps) bad = true;
+
+    if (bt.y == 0) {
+        double2 *Rd = reinterpret_cast<double2 *>(B.R[dst]);
+        double2 *Fn = reinterpret_cast<double2 *>(B.fnode);
+        for (int a = tid; a < n; a += 256) {
+            if (ADVANCE) Rd[a] = sR[a];
+            Fn[a] = sF[a];
+        }
+        if (tid == 0) {
+            B.origin[2 * dst] = nox;
+            B.origin[2 * dst + 1] = noy;
+        }
+    }
+
+    // 3. gather-spread onto this block's 16x16 tile of the patch, node order fixed
+    const int tx = bt.y % B.nside, ty = bt.y / B.nside;
+    const int X0 = nox + tx * kPatchTile, Y0 = noy + ty * kPatchTile;
+    if (tid == 0) sTot = 0;
+    __syncthreads();
+    for (int base = 0; base < n; base += 256) {
+        int a = base + tid;
+        bool flag = false;
+        if (a < n) {
+            double2 R = sR[a];
+            flag = R.x > X0 - 2.0 && R.x < X0 + kPatchTile + 1.0 && R.y > Y0 - 2.0 && R.y < Y0 + kPatchTile + 1.0;
+        }
+        unsigned long long m = __ballot(flag);
+        int pre = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) sCnt[wv] = __popcll(m);
+        __syncthreads();
+        int off = sTot;
+        for (int w = 0; w < wv; ++w) off += sCnt[w];
+        if (flag) sList[off + pre] = a;
+        __syncthreads();
+        if (tid == 0) sTot += sCnt[0] + sCnt[1] + sCnt[2] + sCnt[3];
+        __syncthreads();
+    }
+    const int lx = tid % kPatchTile, ly = tid / kPatchTile;
+    const int px = tx * kPatchTile + lx, py = ty * kPatchTile + ly;
+    if (px < B.ps && py < B.ps) {
+        const double X = (double)(X0 + lx), Y = (double)(Y0 + ly);
+        double fx = 0.0, fy = 0.0;
+        for (int q = 0; q < sTot; ++q) {
+            int a = sList[q];
+            double dx = sR[a].x - X, dy = sR[a].y - Y;
+            if (fabs(dx) < 2.0 && fabs(dy) < 2.0) {
+                double w = phi_d(dx) * phi_d(dy);
+                fx += sF[a].x * w;
+                fy += sF[a].y * w;
+            }
+        }
+        size_t i = (size_t)py * B.ps + px;
+        B.fib[i] = (float)fx;
+        B.fib[(size_t)B.ps * B.ps + i] = (float)fy;
+    }
+    if (bad) atomicOr(d_status, kStatusPatch);
+    (void)S;
+}
+
+// ------------------------------------------------------------------------------------------------
+// fused single-pass step
+// ------------------------------------------------------------------------------------------------
+
+// blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous run of work items so
+// neighbouring strips and segments share that XCD's L2
+__device__ __forceinline__ int xcd_remap(int v, int n) {
+    int q = n >> 3, r = n & 7;
+    int x = v & 7, k = v >> 3;
+    return x * q + min(x, r) + k;
+}
+
+template <int T, typename HT>
+__global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, const BodyDev *__restrict__ bodies,
+                                             const WorkItem *__restrict__ items, int n_items, int cur,
+                                             int *__restrict__ d_t) {
+    __shared__ float rP[5][2][T];    // polarization rows f-4 .. f
+    __shared__ float rS[4][3][T];    // stress rows f-4 .. f-1
+    __shared__ float rE[3][4][T];    // Ericksen stress rows f-3 .. f-1
+    __shared__ float rV[3][2][T];    // velocity rows f-4 .. f-2
+    __shared__ float rQ[3][5][T];    // predicted stress and polarization rows f-5 .. f-3
+    const int tid = threadIdx.x;
+    const int nxt = cur ^ 1;
+    if (blockIdx.x == 0 && tid == 0) d_t[0] = d_t[0] + 1;   // the body update after this step uses t+1
+
+    for (int vi = blockIdx.x; vi < n_items; vi += gridDim.x) {
+        const WorkItem wi = items[xcd_remap(vi, n_items)];
+        const SimDev &S = sims[wi.sim];
+        const int nx = S.nx, ny = S.ny;
+        const size_t N = (size_t)nx * ny;
+        const HT *__restrict__ hin = reinterpret_cast<const HT *>(S.h[cur]);
+        HT *__restrict__ hout = reinterpret_cast<HT *>(S.h[nxt]);
+        const float *__restrict__ sgi = S.sig[cur];
+        float *__restrict__ sgo = S.sig[nxt];
+        const float *__restrict__ Pi = S.P[cur];
+        float *__restrict__ Po = S.P[nxt];
+        const int c = wi.x0 - kHalo + tid;
+        const int x = wrapi(c, nx), xm = wrapi(c - 1, nx), xp = wrapi(c + 1, nx);
+        const int wcol = wi.w;
+        const bool colA = tid < wcol + 2 * kHalo;
+        const bool colB = tid >= 1 && tid < wcol + 7;
+        const bool colC = tid >= 2 && tid < wcol + 6;
+        const bool colD = tid >= 3 && tid < wcol + 5;
+        const bool colE = tid >= 4 && tid < wcol + 4;
+
+        float cvx = 0.f, cvy = 0.f;
+        Grad cg = {0.f, 0.f, 0.f, 0.f};
+        Stiff ck = {0.f, 0.f, 0.f, 0.f};
+        float cs0 = 0.f, cs1 = 0.f, cs2 = 0.f, cp0 = 0.f, cp1 = 0.f;
+
+        __syncthreads();
+        const int niter = wi.l + 8;
+        for (int j = 0; j < niter; ++j) {
+            const int f = wi.y0 - 4 + j;
+            // ring slot of row f - m is (j - m) mod (ring size); 60 keeps the operands positive
+            const int p0 = (j + 60) % 5, p1 = (j + 59) % 5, p2 = (j + 58) % 5, p3 = (j + 57) % 5, p4 = (j + 56) % 5;
+            const int s1 = (j + 59) & 3, s2 = (j + 58) & 3, s3 = (j + 57) & 3, s4 = (j + 56) & 3;
+            const int e1 = (j + 59) % 3, e2 = (j + 58) % 3, e3 = (j + 57) % 3;   // rows f-1, f-2, f-3
+            const int v2 = e2, v3 = e3, v4 = (j + 56) % 3;                       // rows f-2, f-3, f-4
+            const int q3 = e3, q4 = v4, q5 = (j + 55) % 3;                       // rows f-3, f-4, f-5
+
+            // ---- stage A: load P(f), sigma(f-1)
+            if (colA) {
+                const size_t iP = (size_t)wrapi(f, ny) * nx + x;
+                const size_t iS = (size_t)wrapi(f - 1, ny) * nx + x;
+                rP[p0][0][tid] = Pi[iP];
+                rP[p0][1][tid] = Pi[N + iP];
+                rS[s1][0][tid] = sgi[iS];
+                rS[s1][1][tid] = sgi[N + iS];
+                rS[s1][2][tid] = sgi[2 * N + iS];
+            }
+            // populations for stage C (row f-2), pulled: h_n(x, r) = h*_n(x - c_n, r - c_n)
+            float d[9];
+            const bool runC = j >= 4 && colC;
+            if (runC) {
+                const int r = f - 2;
+                const size_t yc = (size_t)wrapi(r, ny) * nx, ym = (size_t)wrapi(r - 1, ny) * nx,
+                             yp = (size_t)wrapi(r + 1, ny) * nx;
+                const float is = S.inv_scale;
+                d[0] = Pop<HT>::load(hin, 0 * N + yc + x, is);
+                d[1] = Pop<HT>::load(hin, 1 * N + yc + xm, is);
+                d[2] = Pop<HT>::load(hin, 2 * N + ym + x, is);
+                d[3] = Pop<HT>::load(hin, 3 * N + yc + xp, is);
+                d[4] = Pop<HT>::load(hin, 4 * N + yp + x, is);
+                d[5] = Pop<HT>::load(hin, 5 * N + ym + xm, is);
+                d[6] = Pop<HT>::load(hin, 6 * N + ym + xp, is);
+                d[7] = Pop<HT>::load(hin, 7 * N + yp + xp, is);
+                d[8] = Pop<HT>::load(hin, 8 * N + yp + xm, is);
+            }
+            __syncthreads();
+
+            // ---- stage B: Ericksen stress at row f-1
+            if (j >= 2 && colB) {
+                float Pc[2] = {rP[p1][0][tid], rP[p1][1][tid]};
+                float Pe[2] = {rP[p1][0][tid + 1], rP[p1][1][tid + 1]};
+                float Pw[2] = {rP[p1][0][tid - 1], rP[p1][1][tid - 1]};
+                float Pn[2] = {rP[p0][0][tid], rP[p0][1][tid]};
+                float Ps[2] = {rP[p2][0][tid], rP[p2][1][tid]};
+                float E[4];
+                ericksen(S, Pc, Pe, Pw, Pn, Ps, E);
+                rE[e1][0][tid] = E[0];
+                rE[e1][1][tid] = E[1];
+                rE[e1][2][tid] = E[2];
+                rE[e1][3][tid] = E[3];
+            }
+            __syncthreads();
+
+            // ---- stage C: force, moments, collision at row f-2
+            if (runC) {
+                const int r = f - 2;
+                const int yw = wrapi(r, ny);
+                float Fx = 0.5f * (rS[s2][0][tid + 1] - rS[s2][0][tid - 1]) + 0.5f * (rS[s1][2][tid] - rS[s3][2][tid]);
+                float Fy = 0.5f * (rS[s2][2][tid + 1] - rS[s2][2][tid - 1]) + 0.5f * (rS[s1][1][tid] - rS[s3][1][tid]);
+                if (S.ericksen) {
+                    Fx += 0.5f * (rE[e2][0][tid + 1] - rE[e2][0][tid - 1]) + 0.5f * (rE[e1][1][tid] - rE[e3][1][tid]);
+                    Fy += 0.5f * (rE[e2][2][tid + 1] - rE[e2][2][tid - 1]) + 0.5f * (rE[e1][3][tid] - rE[e3][3][tid]);
+                }
+                if (S.nb) ib_force(S, bodies, cur, x, yw, Fx, Fy);
+                float drho, ux, uy;
+                collide(d, Fx, Fy, S.omega, S.guo, drho, ux, uy);
+                rV[v2][0][tid] = ux;
+                rV[v2][1][tid] = uy;
+                if (colE && r >= wi.y0 && r < wi.y0 + wi.l) {
+                    const size_t o = (size_t)yw * nx + x;
+                    const float sc = S.scale;
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) Pop<HT>::store(hout, q * N + o, d[q], sc);
+                    if (S.nb) ib_store_v(S, bodies, cur, x, yw, ux, uy);
+                }
+            }
+            __syncthreads();
+
+            // ---- stage D: predictor at row f-3
+            if (j >= 6 && colD) {
+                Grad g = grad_v(rV[v3][0][tid + 1], rV[v3][0][tid - 1], rV[v2][0][tid], rV[v4][0][tid],
+                                rV[v3][1][tid + 1], rV[v3][1][tid - 1], rV[v2][1][tid], rV[v4][1][tid]);
+                const float ux = rV[v3][0][tid], uy = rV[v3][1][tid];
+                float Pc[2] = {rP[p3][0][tid], rP[p3][1][tid]};
+                float Pe[2] = {rP[p3][0][tid + 1], rP[p3][1][tid + 1]};
+                float Pw[2] = {rP[p3][0][tid - 1], rP[p3][1][tid - 1]};
+                float Pn[2] = {rP[p2][0][tid], rP[p2][1][tid]};
+                float Ps[2] = {rP[p4][0][tid], rP[p4][1][tid]};
+                Stiff k = stiffness(S, Pc[0], Pc[1]);
+                float X[3], Xe[3], Xw[3], Xn[3], Xs[3], Rs[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    X[q] = rS[s3][q][tid];
+                    Xe[q] = rS[s3][q][tid + 1];
+                    Xw[q] = rS[s3][q][tid - 1];
+                    Xn[q] = rS[s2][q][tid];
+                    Xs[q] = rS[s4][q][tid];
+                }
+                rhs_sigma(S, k, g, ux, uy, X, Xe, Xw, Xn, Xs, Rs);
+                float Rp[2];
+                rhs_P(S, g, ux, uy, Pc, Pe, Pw, Pn, Ps, Rp);
+                rQ[q3][0][tid] = X[0] + Rs[0];
+                rQ[q3][1][tid] = X[1] + Rs[1];
+                rQ[q3][2][tid] = X[2] + Rs[2];
+                rQ[q3][3][tid] = Pc[0] + Rp[0];
+                rQ[q3][4][tid] = Pc[1] + Rp[1];
+                // corrector inputs frozen at time t, used next iteration for the same row
+                cvx = ux;
+                cvy = uy;
+                cg = g;
+                ck = k;
+                cs0 = X[0];
+                cs1 = X[1];
+                cs2 = X[2];
+                cp0 = Pc[0];
+                cp1 = Pc[1];
+            }
+            __syncthreads();
+
+            // ---- stage E: corrector at row f-4 (inputs of stage D of the previous iteration)
+            if (j >= 8 && colE) {
+                const int r = f - 4;
+                float X[3], Xe[3], Xw[3], Xn[3], Xs[3], Rs[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    X[q] = rQ[q4][q][tid];
+                    Xe[q] = rQ[q4][q][tid + 1];
+                    Xw[q] = rQ[q4][q][tid - 1];
+                    Xn[q] = rQ[q3][q][tid];
+                    Xs[q] = rQ[q5][q][tid];
+                }
+                rhs_sigma(S, ck, cg, cvx, cvy, X, Xe, Xw, Xn, Xs, Rs);
+                float Y[2], Ye[2], Yw[2], Yn[2], Ys[2], Rp[2];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    Y[q] = rQ[q4][3 + q][tid];
+                    Ye[q] = rQ[q4][3 + q][tid + 1];
+                    Yw[q] = rQ[q4][3 + q][tid - 1];
+                    Yn[q] = rQ[q3][3 + q][tid];
+                    Ys[q] = rQ[q5][3 + q][tid];
+                }
+                rhs_P(S, cg, cvx, cvy, Y, Ye, Yw, Yn, Ys, Rp);
+                const size_t o = (size_t)wrapi(r, ny) * nx + x;
+                sgo[o] = 0.5f * ((cs0 + X[0]) + Rs[0]);
+                sgo[N + o] = 0.5f * ((cs1 + X[1]) + Rs[1]);
+                sgo[2 * N + o] = 0.5f * ((cs2 + X[2]) + Rs[2]);
+                Po[o] = 0.5f * ((cp0 + Y[0]) + Rp[0]);
+                Po[N + o] = 0.5f * ((cp1 + Y[1]) + Rp[1]);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// multi-pass reference step: one thread per site, intermediate fields in scratch planes
+// ------------------------------------------------------------------------------------------------
+
+struct Nb {
+    size_t c, e, w, n, s;
+};
+__device__ __forceinline__ Nb nbrs(int x, int y, int nx, int ny) {
+    Nb q;
+    size_t row = (size_t)y * nx;
+    q.c = row + x;
+    q.e = row + wrapi(x + 1, nx);
+    q.w = row + wrapi(x - 1, nx);
+    q.n = (size_t)wrapi(y + 1, ny) * nx + x;
+    q.s = (size_t)wrapi(y - 1, ny) * nx + x;
+    return q;
+}
+
+__device__ __forceinline__ bool site_of(const SiteBlock *blk, const SimDev *sims, int &sim, int &x, int &y) {
+    SiteBlock b = blk[blockIdx.x];
+    const SimDev &S = sims[b.sim];
+    int i = b.start + threadIdx.x;
+    sim = b.sim;
+    if (i >= S.nx * S.ny) return false;
+    y = i / S.nx;
+    x = i - y * S.nx;
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_mp_sigE(const SimDev *__restrict__ sims, const SiteBlock *__restrict__ blk,
+                                                 int cur, int *__restrict__ d_t) {
+    if (d_t && blockIdx.x == 0 && threadIdx.x == 0) d_t[0] = d_t[0] + 1;
+    int sim, x, y;
+    if (!site_of(blk, sims, sim, x, y)) return;
+    const SimDev &S = sims[sim];
+    const size_t N = (size_t)S.nx * S.ny;
+    const float *P = S.P[cur];
+    Nb q = nbrs(x, y, S.nx, S.ny);
+    float Pc[2] = {P[q.c], P[N + q.c]}, Pe[2] = {P[q.e], P[N + q.e]}, Pw[2] = {P[q.w], P[N + q.w]};
+    float Pn[2] = {P[q.n], P[N + q.n]}, Ps[2] = {P[q.s], P[N + q.s]};
+    float E[4];
+    ericksen(S, Pc, Pe, Pw, Pn, Ps, E);
+    for (int k = 0; k < 4; ++k) S.sE[k * N + q.c] = E[k];
+}
+
+// force at a site from the stress, the Ericksen scratch planes and the bodies
+__device__ __forceinline__ void site_force(const SimDev &S, const BodyDev *bodies, int cur, int x, int y, const Nb &q,
+                                           float &Fx, float &Fy, float &fpx, float &fpy) {
+    const size_t N = (size_t)S.nx * S.ny;
+    const float *sg = S.sig[cur];
+    fpx = 0.5f * (sg[q.e] - sg[q.w]) + 0.5f * (sg[2 * N + q.n] - sg[2 * N + q.s]);
+    fpy = 0.5f * (sg[2 * N + q.e] - sg[2 * N + q.w]) + 0.5f * (sg[N + q.n] - sg[N + q.s]);
+    Fx = fpx;
+    Fy = fpy;
+    if (S.ericksen) {
+        const float *E = S.sE;
+        Fx += 0.5f * (E[q.e] - E[q.w]) + 0.5f * (E[N + q.n] - E[N + q.s]);
+        Fy += 0.5f * (E[2 * N + q.e] - E[2 * N + q.w]) + 0.5f * (E[3 * N + q.n] - E[3 * N + q.s]);
+    }
+    if (S.nb) ib_force(S, bodies, cur, x, y, Fx, Fy);
+}
+
+template <typename HT>
+__device__ __forceinline__ void pull_pops(const SimDev &S, const HT *hin, int x, int y, float d[9]) {
+    const size_t N = (size_t)S.nx * S.ny;
+#pragma unroll
+    for (int n = 0; n < 9; ++n) {
+        size_t i = (size_t)wrapi(y - kCY[n], S.ny) * S.nx + wrapi(x - kCX[n], S.nx);
+        d[n] = Pop<HT>::load(hin, n * N + i, S.inv_scale);
+    }
+}
+
+template <typename HT>
+__global__ __launch_bounds__(256) void k_mp_lb(const SimDev *__restrict__ sims, const BodyDev *__restrict__ bodies,
+                                               const SiteBlock *__restrict__ blk, int cur) {
+    int sim, x, y;
+    if (!site_of(blk, sims, sim, x, y)) return;
+    const SimDev &S = sims[sim];
+    const size_t N = (size_t)S.nx * S.ny;
+    Nb q = nbrs(x, y, S.nx, S.ny);
+    float Fx, Fy, fpx, fpy;
+    site_force(S, bodies, cur, x, y, q, Fx, Fy, fpx, fpy);
+    float d[9];
+    pull_pops<HT>(S, reinterpret_cast<const HT *>(S.h[cur]), x, y, d);
+    float drho, ux, uy;
+    collide(d, Fx, Fy, S.omega, S.guo, drho, ux, uy);
+    HT *hout = reinterpret_cast<HT *>(S.h[cur ^ 1]);
+    for (int n = 0; n < 9; ++n) Pop<HT>::store(hout, n * N + q.c, d[n], S.scale);
+    S.v[q.c] = ux;
+    S.v[N + q.c] = uy;
+    if (S.nb) ib_store_v(S, bodies, cur, x, y, ux, uy);
+}
+
+__device__ __forceinline__ Grad grad_at(const SimDev &S, const Nb &q) {
+    const size_t N = (size_t)S.nx * S.ny;
+    const float *v = S.v;
+    return grad_v(v[q.e], v[q.w], v[q.n], v[q.s], v[N + q.e], v[N + q.w], v[N + q.n], v[N + q.s]);
+}
+
+__device__ __forceinline__ void gather3(const float *f, size_t N, const Nb &q, float X[3], float Xe[3], float Xw[3],
+                                        float Xn[3], float Xs[3]) {
+    for (int k = 0; k < 3; ++k) {
+        X[k] = f[k * N + q.c];
+        Xe[k] = f[k * N + q.e];
+        Xw[k] = f[k * N + q.w];
+        Xn[k] = f[k * N + q.n];
+        Xs[k] = f[k * N + q.s];
+    }
+}
+__device__ __forceinline__ void gather2(const float *f, size_t N, const Nb &q, float X[2], float Xe[2], float Xw[2],
+                                        float Xn[2], float Xs[2]) {
+    for (int k = 0; k < 2; ++k) {
+        X[k] = f[k * N + q.c];
+        Xe[k] = f[k * N + q.e];
+        Xw[k] = f[k * N + q.w];
+        Xn[k] = f[k * N + q.n];
+        Xs[k] = f[k * N + q.s];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mp_pred(const SimDev *__restrict__ sims, const SiteBlock *__restrict__ blk,
+                                                 int cur) {
+    int sim, x, y;
+    if (!site_of(blk, sims, sim, x, y)) return;
+    const SimDev &S = sims[sim];
+    const size_t N = (size_t)S.nx * S.ny;
+    Nb q = nbrs(x, y, S.nx, S.ny);
+    Grad g = grad_at(S, q);
+    float ux = S.v[q.c], uy = S.v[N + q.c];
+    float X[3], Xe[3], Xw[3], Xn[3], Xs[3], Rs[3];
+    gather3(S.sig[cur], N, q, X, Xe, Xw, Xn, Xs);
+    float Y[2], Ye[2], Yw[2], Yn[2], Ys[2], Rp[2];
+    gather2(S.P[cur], N, q, Y, Ye, Yw, Yn, Ys);
+    Stiff k = stiffness(S, Y[0], Y[1]);
+    rhs_sigma(S, k, g, ux, uy, X, Xe, Xw, Xn, Xs, Rs);
+    rhs_P(S, g, ux, uy, Y, Ye, Yw, Yn, Ys, Rp);
+    for (int c = 0; c < 3; ++c) S.sp[c * N + q.c] = X[c] + Rs[c];
+    for (int c = 0; c < 2; ++c) S.sp[(3 + c) * N + q.c] = Y[c] + Rp[c];
+}
+
+__global__ __launch_bounds__(256) void k_mp_corr(const SimDev *__restrict__ sims, const SiteBlock *__restrict__ blk,
+                                                 int cur) {
+    int sim, x, y;
+    if (!site_of(blk, sims, sim, x, y)) return;
+    const SimDev &S = sims[sim];
+    const size_t N = (size_t)S.nx * S.ny;
+    Nb q = nbrs(x, y, S.nx, S.ny);
+    Grad g = grad_at(S, q);
+    float ux = S.v[q.c], uy = S.v[N + q.c];
+    const float *P = S.P[cur];
+    Stiff k = stiffness(S, P[q.c], P[N + q.c]);
+    float X[3], Xe[3], Xw[3], Xn[3], Xs[3], Rs[3];
+    gather3(S.sp, N, q, X, Xe, Xw, Xn, Xs);
+    float Y[2], Ye[2], Yw[2], Yn[2], Ys[2], Rp[2];
+    gather2(S.sp + 3 * N, N, q, Y, Ye, Yw, Yn, Ys);
+    rhs_sigma(S, k, g, ux, uy, X, Xe, Xw, Xn, Xs, Rs);
+    rhs_P(S, g, ux, uy, Y, Ye, Yw, Yn, Ys, Rp);
+    const float *sg = S.sig[cur];
+    float *so = S.sig[cur ^ 1], *Po = S.P[cur ^ 1];
+    for (int c = 0; c < 3; ++c) so[c * N + q.c] = 0.5f * ((sg[c * N + q.c] + X[c]) + Rs[c]);
+    for (int c = 0; c < 2; ++c) Po[c * N + q.c] = 0.5f * ((P[c * N + q.c] + Y[c]) + Rp[c]);
+}
+
+// ------------------------------------------------------------------------------------------------
+// observables and reductions
+// ------------------------------------------------------------------------------------------------
+
+// planes of `out` (floats): drho, vx, vy, sxx, syy, sxy, Px, Py, fpx, fpy at the current time
+template <typename HT>
+__global__ __launch_bounds__(256) void k_readout(const SimDev *__restrict__ sims, const BodyDev *__restrict__ bodies,
+                                                 const SiteBlock *__restrict__ blk, int cur, float *__restrict__ out) {
+    int sim, x, y;
+    if (!site_of(blk, sims, sim, x, y)) return;
+    const SimDev &S = sims[sim];
+    const size_t N = (size_t)S.nx * S.ny;
+    Nb q = nbrs(x, y, S.nx, S.ny);
+    float Fx, Fy, fpx, fpy;
+    site_force(S, bodies, cur, x, y, q, Fx, Fy, fpx, fpy);
+    float d[9];
+    pull_pops<HT>(S, reinterpret_cast<const HT *>(S.h[cur]), x, y, d);
+    float drho, ux, uy;
+    collide(d, Fx, Fy, S.omega, S.guo, drho, ux, uy);
+    const float *sg = S.sig[cur], *P = S.P[cur];
+    out[0 * N + q.c] = drho;
+    out[1 * N + q.c] = ux;
+    out[2 * N + q.c] = uy;
+    out[3 * N + q.c] = sg[q.c];
+    out[4 * N + q.c] = sg[N + q.c];
+    out[5 * N + q.c] = sg[2 * N + q.c];
+    out[6 * N + q.c] = P[q.c];
+    out[7 * N + q.c] = P[N + q.c];
+    out[8 * N + q.c] = fpx;
+    out[9 * N + q.c] = fpy;
+}
+
+// block partial sums (FP64) of drho and sum_n c_n d_n over the stored populations of one sim;
+// the stored (post-collision, not yet streamed) populations have the same domain totals
+template <typename HT>
+__global__ __launch_bounds__(256) void k_sums(const SimDev *__restrict__ sims, int sim, int cur,
+                                              double *__restrict__ partial) {
+    __shared__ double sh[3][4];
+    const SimDev &S = sims[sim];
+    const size_t N = (size_t)S.nx * S.ny;
+    const HT *h = reinterpret_cast<const HT *>(S.h[cur]);
+    double m = 0.0, jx = 0.0, jy = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (size_t)gridDim.x * 256) {
+        float d[9];
+#pragma unroll
+        for (int n = 0; n < 9; ++n) d[n] = Pop<HT>::load(h, n * N + i, S.inv_scale);
+#pragma unroll
+        for (int n = 0; n < 9; ++n) {
+            m += (double)d[n];
+            jx += (double)(kCX[n] * d[n]);
+            jy += (double)(kCY[n] * d[n]);
+        }
+    }
+    m = wave_sum(m);
+    jx = wave_sum(jx);
+    jy = wave_sum(jy);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[0][wv] = m;
+        sh[1][wv] = jx;
+        sh[2][wv] = jy;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double s = (sh[threadIdx.x][0] + sh[threadIdx.x][1]) + (sh[threadIdx.x][2] + sh[threadIdx.x][3]);
+        partial[3 * blockIdx.x + threadIdx.x] = s;
+    }
+}
+
+// sum the block partials in a fixed order; out = (sum rho, momentum x, momentum y).  With
+// check_mass > 0, raise the watchdog when the mass is not finite or drifts by more than 1e-6.
+__global__ __launch_bounds__(64) void k_sums_final(const SimDev *__restrict__ sims, int sim, const double *__restrict__ partial,
+                                                   int nblocks, double *__restrict__ out, double check_mass,
+                                                   int *__restrict__ d_status) {
+    const int lane = threadIdx.x;
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int b = lane; b < nblocks; b += 64)
+        for (int k = 0; k < 3; ++k) a[k] += partial[3 * b + k];
+    for (int k = 0; k < 3; ++k) a[k] = wave_sum(a[k]);
+    if (lane == 0) {
+        const SimDev &S = sims[sim];
+        double mass = (double)S.nx * (double)S.ny + a[0];
+        out[0] = mass;
+        out[1] = a[1];
+        out[2] = a[2];
+        if (check_mass > 0.0) {
+            bool ok = isfinite(mass) && isfinite(a[1]) && isfinite(a[2]) && fabs(mass - check_mass) <= 1e-6 * check_mass;
+            if (!ok) atomicOr(d_status, kStatusUnstable);
+        }
+    }
+}
+
+// body observables: restoring force (sum of div sigma over sites inside the node polygon),
+// centre of mass, total node force; one 256-thread block
+__global__ __launch_bounds__(256) void k_body_force(const SimDev *__restrict__ sims, const BodyDev *__restrict__ bodies,
+                                                    int body, int cur, double *__restrict__ out) {
+    __shared__ double2 sR[kMaxNodes];
+    __shared__ double sh[8][4];
+    const BodyDev &B = bodies[body];
+    const SimDev &S = sims[B.sim];
+    const int n = B.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const double2 *R = reinterpret_cast<const double2 *>(B.R[cur]);
+    const double2 *Fn = reinterpret_cast<const double2 *>(B.fnode);
+    double mnx = 1e300, mny = 1e300, mxx = -1e300, mxy = -1e300, cx = 0, cy = 0, fx = 0, fy = 0;
+    for (int a = tid; a < n; a += 256) {
+        double2 r = R[a];
+        sR[a] = r;
+        mnx = fmin(mnx, r.x);
+        mny = fmin(mny, r.y);
+        mxx = fmax(mxx, r.x);
+        mxy = fmax(mxy, r.y);
+        cx += r.x;
+        cy += r.y;
+        fx += Fn[a].x;
+        fy += Fn[a].y;
+    }
+    double v8[8] = {wave_min(mnx), wave_min(mny), wave_max(mxx), wave_max(mxy),
+                    wave_sum(cx), wave_sum(cy), wave_sum(fx), wave_sum(fy)};
+    if (lane == 0)
+        for (int k = 0; k < 8; ++k) sh[k][wv] = v8[k];
+    __syncthreads();
+    mnx = fmin(fmin(sh[0][0], sh[0][1]), fmin(sh[0][2], sh[0][3]));
+    mny = fmin(fmin(sh[1][0], sh[1][1]), fmin(sh[1][2], sh[1][3]));
+    mxx = fmax(fmax(sh[2][0], sh[2][1]), fmax(sh[2][2], sh[2][3]));
+    mxy = fmax(fmax(sh[3][0], sh[3][1]), fmax(sh[3][2], sh[3][3]));
+    double scx = (sh[4][0] + sh[4][1]) + (sh[4][2] + sh[4][3]);
+    double scy = (sh[5][0] + sh[5][1]) + (sh[5][2] + sh[5][3]);
+    double sfx = (sh[6][0] + sh[6][1]) + (sh[6][2] + sh[6][3]);
+    double sfy = (sh[7][0] + sh[7][1]) + (sh[7][2] + sh[7][3]);
+    __syncthreads();
+    const int x0 = (int)ceil(mnx), x1 = (int)floor(mxx), y0 = (int)ceil(mny), y1 = (int)floor(mxy);
+    const int wdt = x1 - x0 + 1, hgt = y1 - y0 + 1;
+    const size_t N = (size_t)S.nx * S.ny;
+    const float *sg = S.sig[cur];
+    double ax = 0.0, ay = 0.0;
+    for (int i = tid; i < wdt * hgt; i += 256) {
+        const int X = x0 + i % wdt, Y = y0 + i / wdt;
+        bool in = false;
+        for (int a = 0, b = n - 1; a < n; b = a++) {
+            double xa = sR[a].x, ya = sR[a].y, xb = sR[b].x, yb = sR[b].y;
+            if ((ya > Y) != (yb > Y) && X < (xb - xa) * (Y - ya) / (yb - ya) + xa) in = !in;
+        }
+        if (!in) continue;
+        Nb q = nbrs(wrapi(X, S.nx), wrapi(Y, S.ny), S.nx, S.ny);
+        ax += 0.5 * ((double)sg[q.e] - (double)sg[q.w]) + 0.5 * ((double)sg[2 * N + q.n] - (double)sg[2 * N + q.s]);
+        ay += 0.5 * ((double)sg[2 * N + q.e] - (double)sg[2 * N + q.w]) + 0.5 * ((double)sg[N + q.n] - (double)sg[N + q.s]);
+    }
+    ax = wave_sum(ax);
+    ay = wave_sum(ay);
+    if (lane == 0) {
+        sh[0][wv] = ax;
+        sh[1][wv] = ay;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        out[0] = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+        out[1] = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+        out[2] = scx / n;
+        out[3] = scy / n;
+        out[4] = sfx;
+        out[5] = sfy;
+    }
+}
+
+// convert host-prepared FP32 population offsets (already un-streamed) to the storage type
+template <typename HT>
+__global__ __launch_bounds__(256) void k_pack(const float *__restrict__ src, HT *__restrict__ dst, size_t n, float scale) {
+    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) Pop<HT>::store(dst, i, src[i], scale);
+}
+
+// ------------------------------------------------------------------------------------------------
+// launch wrappers (host)
+// ------------------------------------------------------------------------------------------------
+
+hipError_t launch_ib(bool advance, int nblocks, hipStream_t st, const SimDev *sims, BodyDev *bodies, const int2 *blk,
+                     int cur, const int *d_t, int *d_status) {
+    if (nblocks <= 0) return hipSuccess;
+    if (advance)
+        k_ib<true><<<nblocks, 256, 0, st>>>(sims, bodies, blk, cur, d_t, d_status);
+    else
+        k_ib<false><<<nblocks, 256, 0, st>>>(sims, bodies, blk, cur, d_t, d_status);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused(int T, bool fp16, int grid, hipStream_t st, const SimDev *sims, const BodyDev *bodies,
+                        const WorkItem *items, int n_items, int cur, int *d_t) {
+    if (T == 128) {
+        if (fp16)
+            k_fused<128, __half><<<grid, 128, 0, st>>>(sims, bodies, items, n_items, cur, d_t);
+        else
+            k_fused<128, float><<<grid, 128, 0, st>>>(sims, bodies, items, n_items, cur, d_t);
+    } else if (T == 256) {
+        if (fp16)
+            k_fused<256, __half><<<grid, 256, 0, st>>>(sims, bodies, items, n_items, cur, d_t);
+        else
+            k_fused<256, float><<<grid, 256, 0, st>>>(sims, bodies, items, n_items, cur, d_t);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_multipass(bool fp16, int nblocks, hipStream_t st, const SimDev *sims, const BodyDev *bodies,
+                            const SiteBlock *blk, int cur, int *d_t) {
+    k_mp_sigE<<<nblocks, 256, 0, st>>>(sims, blk, cur, d_t);
+    if (fp16)
+        k_mp_lb<__half><<<nblocks, 256, 0, st>>>(sims, bodies, blk, cur);
+    else
+        k_mp_lb<float><<<nblocks, 256, 0, st>>>(sims, bodies, blk, cur);
+    k_mp_pred<<<nblocks, 256, 0, st>>>(sims, blk, cur);
+    k_mp_corr<<<nblocks, 256, 0, st>>>(sims, blk, cur);
+    return hipGetLastError();
+}
+
+hipError_t launch_readout(bool fp16, int nblocks, int block0, hipStream_t st, const SimDev *sims, const BodyDev *bodies,
+                          const SiteBlock *blk, int cur, float *out) {
+    k_mp_sigE<<<nblocks, 256, 0, st>>>(sims, blk + block0, cur, nullptr);
+    if (fp16)
+        k_readout<__half><<<nblocks, 256, 0, st>>>(sims, bodies, blk + block0, cur, out);
+    else
+        k_readout<float><<<nblocks, 256, 0, st>>>(sims, bodies, blk + block0, cur, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sums(bool fp16, int sim, int nblocks, hipStream_t st, const SimDev *sims, int cur, double *partial,
+                       double *out, double check_mass, int *d_status) {
+    if (fp16)
+        k_sums<__half><<<nblocks, 256, 0, st>>>(sims, sim, cur, partial);
+    else
+        k_sums<float><<<nblocks, 256, 0, st>>>(sims, sim, cur, partial);
+    k_sums_final<<<1, 64, 0, st>>>(sims, sim, partial, nblocks, out, check_mass, d_status);
+    return hipGetLastError();
+}
+
+hipError_t launch_body_force(hipStream_t st, const SimDev *sims, const BodyDev *bodies, int body, int cur, double *out) {
+    k_body_force<<<1, 256, 0, st>>>(sims, bodies, body, cur, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(bool fp16, hipStream_t st, const float *src, void *dst, size_t n, float scale) {
+    int nb = (int)((n + 255) / 256);
+    if (fp16)
+        k_pack<__half><<<nb, 256, 0, st>>>(src, reinterpret_cast<__half *>(dst), n, scale);
+    else
+        k_pack<float><<<nb, 256, 0, st>>>(src, reinterpret_cast<float *>(dst), n, scale);
+    return hipGetLastError();
+}
+
+}  // namespace lbk

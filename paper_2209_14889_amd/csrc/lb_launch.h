@@ -1,0 +1,23 @@
+// Host-callable launch wrappers of the liblb kernels (defined in lb_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lb_common.h"
+
+namespace lbk {
+
+hipError_t launch_ib(bool advance, int nblocks, hipStream_t st, const SimDev *sims, BodyDev *bodies, const int2 *blk,
+                     int cur, const int *d_t, int *d_status);
+hipError_t launch_fused(int T, bool fp16, int grid, hipStream_t st, const SimDev *sims, const BodyDev *bodies,
+                        const WorkItem *items, int n_items, int cur, int *d_t);
+hipError_t launch_multipass(bool fp16, int nblocks, hipStream_t st, const SimDev *sims, const BodyDev *bodies,
+                            const SiteBlock *blk, int cur, int *d_t);
+hipError_t launch_readout(bool fp16, int nblocks, int block0, hipStream_t st, const SimDev *sims,
+                          const BodyDev *bodies, const SiteBlock *blk, int cur, float *out);
+hipError_t launch_sums(bool fp16, int sim, int nblocks, hipStream_t st, const SimDev *sims, int cur, double *partial,
+                       double *out, double check_mass, int *d_status);
+hipError_t launch_body_force(hipStream_t st, const SimDev *sims, const BodyDev *bodies, int body, int cur,
+                             double *out);
+hipError_t launch_pack(bool fp16, hipStream_t st, const float *src, void *dst, size_t n, float scale);
+
+}  // namespace lbk
