@@ -152,7 +152,7 @@ struct BodyPlan {
 struct SimPlan {
     int nx, ny;
     size_t N;
-    size_t oH0, oH1, oS0, oS1, oP0, oP1, oSE, oV, oSP;
+    size_t oH0, oH1, oS0, oS1, oP0, oP1, oSE, oV, oSP, oSPP;
     int tab;     // index into the handle's table list
     int blk0, nblk;
 };
@@ -271,11 +271,12 @@ Plan make_plan(const lb_sim_params *sims, int n_sims, const Opt &o) {
         sp.oH1 = a.take(9 * sp.N * hb);
         sp.oS0 = a.take(3 * sp.N * 4);
         sp.oS1 = a.take(3 * sp.N * 4);
-        sp.oP0 = a.take(2 * sp.N * 4);
-        sp.oP1 = a.take(2 * sp.N * 4);
+        sp.oP0 = a.take(2 * sp.N * 8);
+        sp.oP1 = a.take(2 * sp.N * 8);
         sp.oSE = a.take(4 * sp.N * 4);
         sp.oV = a.take(o.kernel == 1 ? 2 * sp.N * 4 : 0);
-        sp.oSP = a.take(o.kernel == 1 ? 5 * sp.N * 4 : 0);
+        sp.oSP = a.take(o.kernel == 1 ? 3 * sp.N * 4 : 0);
+        sp.oSPP = a.take(o.kernel == 1 ? 2 * sp.N * 8 : 0);
         sp.tab = (int)(std::find(pl.clamps.begin(), pl.clamps.end(), p.P_clamp) - pl.clamps.begin());
         sp.blk0 = nblk_sites;
         sp.nblk = (int)((sp.N + 255) / 256);
@@ -610,20 +611,22 @@ static int create_impl(const lb_sim_params *sims, int n_sims, const lb_options *
         d.h[1] = A.ptr<void>(sp.oH1);
         d.sig[0] = A.ptr<float>(sp.oS0);
         d.sig[1] = A.ptr<float>(sp.oS1);
-        d.P[0] = A.ptr<float>(sp.oP0);
-        d.P[1] = A.ptr<float>(sp.oP1);
+        d.P[0] = A.ptr<double>(sp.oP0);
+        d.P[1] = A.ptr<double>(sp.oP1);
         d.sE = A.ptr<float>(sp.oSE);
         d.v = o.kernel == 1 ? A.ptr<float>(sp.oV) : nullptr;
-        d.sp = o.kernel == 1 ? A.ptr<float>(sp.oSP) : nullptr;
+        d.sps = o.kernel == 1 ? A.ptr<float>(sp.oSP) : nullptr;
+        d.spp = o.kernel == 1 ? A.ptr<double>(sp.oSPP) : nullptr;
         h->hs.push_back(d);
 
-        // P and sigma
+        // P (FP64) and sigma
+        {
+            std::vector<double> pb(2 * N, 0.0);
+            if (p.init_P) std::copy(p.init_P, p.init_P + 2 * N, pb.begin());
+            HIPCHK(hipMemcpyAsync(d.P[0], pb.data(), 2 * N * 8, hipMemcpyHostToDevice, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+        }
         buf.assign(3 * N, 0.0f);
-        if (p.init_P)
-            for (size_t i = 0; i < 2 * N; ++i) buf[i] = (float)p.init_P[i];
-        HIPCHK(hipMemcpyAsync(d.P[0], buf.data(), 2 * N * 4, hipMemcpyHostToDevice, h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
-        std::fill(buf.begin(), buf.end(), 0.0f);
         if (p.init_sigma)
             for (size_t i = 0; i < 3 * N; ++i) buf[i] = (float)p.init_sigma[i];
         HIPCHK(hipMemcpyAsync(d.sig[0], buf.data(), 3 * N * 4, hipMemcpyHostToDevice, h->stream));

@@ -33,10 +33,12 @@ struct SimDev {
     const float4 *tab;              // per interval: (A2, dA2, A4, dA4), A2 = a2/s, A4 = a4/s^2
     void *h[2];                     // post-collision population offsets, 9 planes (float or half)
     float *sig[2];                  // polymer stress planes sxx, syy, sxy
-    float *P[2];                    // polarization planes Px, Py
-    float *sE;                      // multi-pass scratch: Ericksen stress xx, xy, yx, yy
+    double *P[2];                   // polarization planes Px, Py; FP64 because its per-step
+                                    // increments fall below the FP32 resolution of |P| ~ 1
+    float *sE;                      // scratch: Ericksen stress xx, xy, yx, yy
     float *v;                       // multi-pass scratch: velocity
-    float *sp;                      // multi-pass scratch: predicted sigma (3) and P (2)
+    float *sps;                     // multi-pass scratch: predicted stress (3 planes)
+    double *spp;                    // multi-pass scratch: predicted polarization (2 planes)
 };
 
 struct BodyDev {

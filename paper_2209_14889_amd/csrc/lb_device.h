@@ -150,39 +150,44 @@ __device__ __forceinline__ void rhs_sigma(const SimDev &S, const Stiff &k, const
 }
 
 // right-hand side of eqBE: -(v.grad)Y - Omega Y + xi Psi Y - Gamma h(Y),
-// h = (alpha + beta |Y|^2) Y - kappa lap Y
+// h = (alpha + beta |Y|^2) Y - kappa lap Y.  FP64: near the equilibrium magnitude the factor
+// alpha + beta |Y|^2 is a small difference of O(1) numbers, and per-step increments of Y are far
+// below the FP32 resolution of |Y|.
 __device__ __forceinline__ void rhs_P(const SimDev &S, const Grad &g, float ux, float uy,
-                                      const float Y[2], const float Ye[2], const float Yw[2],
-                                      const float Yn[2], const float Ys[2], float R[2]) {
-    float a = S.alpha + S.beta * (Y[0] * Y[0] + Y[1] * Y[1]);
-    float lap0 = ((Ye[0] + Yw[0]) + (Yn[0] + Ys[0])) - 4.0f * Y[0];
-    float lap1 = ((Ye[1] + Yw[1]) + (Yn[1] + Ys[1])) - 4.0f * Y[1];
-    float h0 = a * Y[0] - S.kappa * lap0;
-    float h1 = a * Y[1] - S.kappa * lap1;
-    float adv0 = ux * (0.5f * (Ye[0] - Yw[0])) + uy * (0.5f * (Yn[0] - Ys[0]));
-    float adv1 = ux * (0.5f * (Ye[1] - Yw[1])) + uy * (0.5f * (Yn[1] - Ys[1]));
-    R[0] = -adv0 - g.om * Y[1] + S.xi * (g.psi0 * Y[0] + g.psi2 * Y[1]) - S.Gamma * h0;
-    R[1] = -adv1 + g.om * Y[0] + S.xi * (g.psi2 * Y[0] + g.psi1 * Y[1]) - S.Gamma * h1;
+                                      const double Y[2], const double Ye[2], const double Yw[2],
+                                      const double Yn[2], const double Ys[2], double R[2]) {
+    const double a = (double)S.alpha + (double)S.beta * (Y[0] * Y[0] + Y[1] * Y[1]);
+    const double kap = S.kappa, xi = S.xi, Gam = S.Gamma;
+    const double om = g.om, p0 = g.psi0, p1 = g.psi1, p2 = g.psi2, vx = ux, vy = uy;
+    double lap0 = ((Ye[0] + Yw[0]) + (Yn[0] + Ys[0])) - 4.0 * Y[0];
+    double lap1 = ((Ye[1] + Yw[1]) + (Yn[1] + Ys[1])) - 4.0 * Y[1];
+    double h0 = a * Y[0] - kap * lap0;
+    double h1 = a * Y[1] - kap * lap1;
+    double adv0 = vx * (0.5 * (Ye[0] - Yw[0])) + vy * (0.5 * (Yn[0] - Ys[0]));
+    double adv1 = vx * (0.5 * (Ye[1] - Yw[1])) + vy * (0.5 * (Yn[1] - Ys[1]));
+    R[0] = -adv0 - om * Y[1] + xi * (p0 * Y[0] + p2 * Y[1]) - Gam * h0;
+    R[1] = -adv1 + om * Y[0] + xi * (p2 * Y[0] + p1 * Y[1]) - Gam * h1;
 }
 
-// Ericksen stress at a site (Sec. II C 1, with kappa on the gradient term):
+// Ericksen stress at a site (Sec. II C 1, with kappa on the gradient term), from FP64 P:
 // out = (xx, xy, yx, yy)
-__device__ __forceinline__ void ericksen(const SimDev &S, const float P[2], const float Pe[2], const float Pw[2],
-                                         const float Pn[2], const float Ps[2], float E[4]) {
-    float a = S.alpha + S.beta * (P[0] * P[0] + P[1] * P[1]);
-    float lap0 = ((Pe[0] + Pw[0]) + (Pn[0] + Ps[0])) - 4.0f * P[0];
-    float lap1 = ((Pe[1] + Pw[1]) + (Pn[1] + Ps[1])) - 4.0f * P[1];
-    float hx = a * P[0] - S.kappa * lap0;
-    float hy = a * P[1] - S.kappa * lap1;
-    float dxPx = 0.5f * (Pe[0] - Pw[0]), dyPx = 0.5f * (Pn[0] - Ps[0]);
-    float dxPy = 0.5f * (Pe[1] - Pw[1]), dyPy = 0.5f * (Pn[1] - Ps[1]);
-    float anti = -0.5f * (P[0] * hy - hx * P[1]);
-    float sym = 0.5f * S.xi * (P[0] * hy + hx * P[1]);
-    float gxy = S.kappa * (dxPx * dyPx + dxPy * dyPy);
-    E[0] = S.xi * P[0] * hx - S.kappa * (dxPx * dxPx + dxPy * dxPy);
-    E[1] = anti + sym - gxy;
-    E[2] = -anti + sym - gxy;
-    E[3] = S.xi * P[1] * hy - S.kappa * (dyPx * dyPx + dyPy * dyPy);
+__device__ __forceinline__ void ericksen(const SimDev &S, const double P[2], const double Pe[2], const double Pw[2],
+                                         const double Pn[2], const double Ps[2], float E[4]) {
+    const double a = (double)S.alpha + (double)S.beta * (P[0] * P[0] + P[1] * P[1]);
+    const double kap = S.kappa, xi = S.xi;
+    double lap0 = ((Pe[0] + Pw[0]) + (Pn[0] + Ps[0])) - 4.0 * P[0];
+    double lap1 = ((Pe[1] + Pw[1]) + (Pn[1] + Ps[1])) - 4.0 * P[1];
+    double hx = a * P[0] - kap * lap0;
+    double hy = a * P[1] - kap * lap1;
+    double dxPx = 0.5 * (Pe[0] - Pw[0]), dyPx = 0.5 * (Pn[0] - Ps[0]);
+    double dxPy = 0.5 * (Pe[1] - Pw[1]), dyPy = 0.5 * (Pn[1] - Ps[1]);
+    double anti = -0.5 * (P[0] * hy - hx * P[1]);
+    double sym = 0.5 * xi * (P[0] * hy + hx * P[1]);
+    double gxy = kap * (dxPx * dyPx + dxPy * dyPy);
+    E[0] = (float)(xi * P[0] * hx - kap * (dxPx * dxPx + dxPy * dxPy));
+    E[1] = (float)(anti + sym - gxy);
+    E[2] = (float)(-anti + sym - gxy);
+    E[3] = (float)(xi * P[1] * hy - kap * (dyPx * dyPx + dyPy * dyPy));
 }
 
 // immersed-boundary force at lattice site (x, y) from the bodies' spread-force patches

@@ -256,11 +256,12 @@ template <int T, typename HT>
 __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, const BodyDev *__restrict__ bodies,
                                              const WorkItem *__restrict__ items, int n_items, int cur,
                                              int *__restrict__ d_t) {
-    __shared__ float rP[5][2][T];    // polarization rows f-4 .. f
+    __shared__ double rP[5][2][T];   // polarization rows f-4 .. f
     __shared__ float rS[4][3][T];    // stress rows f-4 .. f-1
     __shared__ float rE[3][4][T];    // Ericksen stress rows f-3 .. f-1
     __shared__ float rV[3][2][T];    // velocity rows f-4 .. f-2
-    __shared__ float rQ[3][5][T];    // predicted stress and polarization rows f-5 .. f-3
+    __shared__ float rQs[3][3][T];   // predicted stress rows f-5 .. f-3
+    __shared__ double rQp[3][2][T];  // predicted polarization rows f-5 .. f-3
     const int tid = threadIdx.x;
     const int nxt = cur ^ 1;
     if (blockIdx.x == 0 && tid == 0) d_t[0] = d_t[0] + 1;   // the body update after this step uses t+1
@@ -274,8 +275,8 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
         HT *__restrict__ hout = reinterpret_cast<HT *>(S.h[nxt]);
         const float *__restrict__ sgi = S.sig[cur];
         float *__restrict__ sgo = S.sig[nxt];
-        const float *__restrict__ Pi = S.P[cur];
-        float *__restrict__ Po = S.P[nxt];
+        const double *__restrict__ Pi = S.P[cur];
+        double *__restrict__ Po = S.P[nxt];
         const int c = wi.x0 - kHalo + tid;
         const int x = wrapi(c, nx), xm = wrapi(c - 1, nx), xp = wrapi(c + 1, nx);
         const int wcol = wi.w;
@@ -285,10 +286,13 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
         const bool colD = tid >= 3 && tid < wcol + 5;
         const bool colE = tid >= 4 && tid < wcol + 4;
 
-        float cvx = 0.f, cvy = 0.f;
+        // corrector inputs frozen at time t: produced by stage D for row r in one iteration and
+        // consumed by stage E for the same row in the next one (stage D of that iteration has
+        // already moved on to row r+1, hence the separate "next" copies)
+        float cvx = 0.f, cvy = 0.f, cs0 = 0.f, cs1 = 0.f, cs2 = 0.f;
+        double cp0 = 0.0, cp1 = 0.0;
         Grad cg = {0.f, 0.f, 0.f, 0.f};
         Stiff ck = {0.f, 0.f, 0.f, 0.f};
-        float cs0 = 0.f, cs1 = 0.f, cs2 = 0.f, cp0 = 0.f, cp1 = 0.f;
 
         __syncthreads();
         const int niter = wi.l + 8;
@@ -333,11 +337,11 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
 
             // ---- stage B: Ericksen stress at row f-1
             if (j >= 2 && colB) {
-                float Pc[2] = {rP[p1][0][tid], rP[p1][1][tid]};
-                float Pe[2] = {rP[p1][0][tid + 1], rP[p1][1][tid + 1]};
-                float Pw[2] = {rP[p1][0][tid - 1], rP[p1][1][tid - 1]};
-                float Pn[2] = {rP[p0][0][tid], rP[p0][1][tid]};
-                float Ps[2] = {rP[p2][0][tid], rP[p2][1][tid]};
+                double Pc[2] = {rP[p1][0][tid], rP[p1][1][tid]};
+                double Pe[2] = {rP[p1][0][tid + 1], rP[p1][1][tid + 1]};
+                double Pw[2] = {rP[p1][0][tid - 1], rP[p1][1][tid - 1]};
+                double Pn[2] = {rP[p0][0][tid], rP[p0][1][tid]};
+                double Ps[2] = {rP[p2][0][tid], rP[p2][1][tid]};
                 float E[4];
                 ericksen(S, Pc, Pe, Pw, Pn, Ps, E);
                 rE[e1][0][tid] = E[0];
@@ -373,16 +377,21 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             __syncthreads();
 
             // ---- stage D: predictor at row f-3
+            float nvx = 0.f, nvy = 0.f, ns0 = 0.f, ns1 = 0.f, ns2 = 0.f;
+            double np0 = 0.0, np1 = 0.0;
+            Grad ng = {0.f, 0.f, 0.f, 0.f};
+            Stiff nk = {0.f, 0.f, 0.f, 0.f};
             if (j >= 6 && colD) {
-                Grad g = grad_v(rV[v3][0][tid + 1], rV[v3][0][tid - 1], rV[v2][0][tid], rV[v4][0][tid],
-                                rV[v3][1][tid + 1], rV[v3][1][tid - 1], rV[v2][1][tid], rV[v4][1][tid]);
-                const float ux = rV[v3][0][tid], uy = rV[v3][1][tid];
-                float Pc[2] = {rP[p3][0][tid], rP[p3][1][tid]};
-                float Pe[2] = {rP[p3][0][tid + 1], rP[p3][1][tid + 1]};
-                float Pw[2] = {rP[p3][0][tid - 1], rP[p3][1][tid - 1]};
-                float Pn[2] = {rP[p2][0][tid], rP[p2][1][tid]};
-                float Ps[2] = {rP[p4][0][tid], rP[p4][1][tid]};
-                Stiff k = stiffness(S, Pc[0], Pc[1]);
+                ng = grad_v(rV[v3][0][tid + 1], rV[v3][0][tid - 1], rV[v2][0][tid], rV[v4][0][tid],
+                            rV[v3][1][tid + 1], rV[v3][1][tid - 1], rV[v2][1][tid], rV[v4][1][tid]);
+                nvx = rV[v3][0][tid];
+                nvy = rV[v3][1][tid];
+                double Pc[2] = {rP[p3][0][tid], rP[p3][1][tid]};
+                double Pe[2] = {rP[p3][0][tid + 1], rP[p3][1][tid + 1]};
+                double Pw[2] = {rP[p3][0][tid - 1], rP[p3][1][tid - 1]};
+                double Pn[2] = {rP[p2][0][tid], rP[p2][1][tid]};
+                double Ps[2] = {rP[p4][0][tid], rP[p4][1][tid]};
+                nk = stiffness(S, (float)Pc[0], (float)Pc[1]);
                 float X[3], Xe[3], Xw[3], Xn[3], Xs[3], Rs[3];
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
@@ -392,57 +401,62 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                     Xn[q] = rS[s2][q][tid];
                     Xs[q] = rS[s4][q][tid];
                 }
-                rhs_sigma(S, k, g, ux, uy, X, Xe, Xw, Xn, Xs, Rs);
-                float Rp[2];
-                rhs_P(S, g, ux, uy, Pc, Pe, Pw, Pn, Ps, Rp);
-                rQ[q3][0][tid] = X[0] + Rs[0];
-                rQ[q3][1][tid] = X[1] + Rs[1];
-                rQ[q3][2][tid] = X[2] + Rs[2];
-                rQ[q3][3][tid] = Pc[0] + Rp[0];
-                rQ[q3][4][tid] = Pc[1] + Rp[1];
-                // corrector inputs frozen at time t, used next iteration for the same row
-                cvx = ux;
-                cvy = uy;
-                cg = g;
-                ck = k;
-                cs0 = X[0];
-                cs1 = X[1];
-                cs2 = X[2];
-                cp0 = Pc[0];
-                cp1 = Pc[1];
+                rhs_sigma(S, nk, ng, nvx, nvy, X, Xe, Xw, Xn, Xs, Rs);
+                double Rp[2];
+                rhs_P(S, ng, nvx, nvy, Pc, Pe, Pw, Pn, Ps, Rp);
+                rQs[q3][0][tid] = X[0] + Rs[0];
+                rQs[q3][1][tid] = X[1] + Rs[1];
+                rQs[q3][2][tid] = X[2] + Rs[2];
+                rQp[q3][0][tid] = Pc[0] + Rp[0];
+                rQp[q3][1][tid] = Pc[1] + Rp[1];
+                ns0 = X[0];
+                ns1 = X[1];
+                ns2 = X[2];
+                np0 = Pc[0];
+                np1 = Pc[1];
             }
             __syncthreads();
 
-            // ---- stage E: corrector at row f-4 (inputs of stage D of the previous iteration)
+            // ---- stage E: corrector at row f-4, with the inputs stage D froze one iteration ago
             if (j >= 8 && colE) {
                 const int r = f - 4;
                 float X[3], Xe[3], Xw[3], Xn[3], Xs[3], Rs[3];
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
-                    X[q] = rQ[q4][q][tid];
-                    Xe[q] = rQ[q4][q][tid + 1];
-                    Xw[q] = rQ[q4][q][tid - 1];
-                    Xn[q] = rQ[q3][q][tid];
-                    Xs[q] = rQ[q5][q][tid];
+                    X[q] = rQs[q4][q][tid];
+                    Xe[q] = rQs[q4][q][tid + 1];
+                    Xw[q] = rQs[q4][q][tid - 1];
+                    Xn[q] = rQs[q3][q][tid];
+                    Xs[q] = rQs[q5][q][tid];
                 }
                 rhs_sigma(S, ck, cg, cvx, cvy, X, Xe, Xw, Xn, Xs, Rs);
-                float Y[2], Ye[2], Yw[2], Yn[2], Ys[2], Rp[2];
+                double Y[2], Ye[2], Yw[2], Yn[2], Ys[2], Rp[2];
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
-                    Y[q] = rQ[q4][3 + q][tid];
-                    Ye[q] = rQ[q4][3 + q][tid + 1];
-                    Yw[q] = rQ[q4][3 + q][tid - 1];
-                    Yn[q] = rQ[q3][3 + q][tid];
-                    Ys[q] = rQ[q5][3 + q][tid];
+                    Y[q] = rQp[q4][q][tid];
+                    Ye[q] = rQp[q4][q][tid + 1];
+                    Yw[q] = rQp[q4][q][tid - 1];
+                    Yn[q] = rQp[q3][q][tid];
+                    Ys[q] = rQp[q5][q][tid];
                 }
                 rhs_P(S, cg, cvx, cvy, Y, Ye, Yw, Yn, Ys, Rp);
                 const size_t o = (size_t)wrapi(r, ny) * nx + x;
                 sgo[o] = 0.5f * ((cs0 + X[0]) + Rs[0]);
                 sgo[N + o] = 0.5f * ((cs1 + X[1]) + Rs[1]);
                 sgo[2 * N + o] = 0.5f * ((cs2 + X[2]) + Rs[2]);
-                Po[o] = 0.5f * ((cp0 + Y[0]) + Rp[0]);
-                Po[N + o] = 0.5f * ((cp1 + Y[1]) + Rp[1]);
+                Po[o] = 0.5 * ((cp0 + Y[0]) + Rp[0]);
+                Po[N + o] = 0.5 * ((cp1 + Y[1]) + Rp[1]);
             }
+            // commit the frozen inputs of row f-3 for next iteration's corrector
+            cvx = nvx;
+            cvy = nvy;
+            cg = ng;
+            ck = nk;
+            cs0 = ns0;
+            cs1 = ns1;
+            cs2 = ns2;
+            cp0 = np0;
+            cp1 = np1;
         }
     }
 }
@@ -483,10 +497,10 @@ __global__ __launch_bounds__(256) void k_mp_sigE(const SimDev *__restrict__ sims
     if (!site_of(blk, sims, sim, x, y)) return;
     const SimDev &S = sims[sim];
     const size_t N = (size_t)S.nx * S.ny;
-    const float *P = S.P[cur];
+    const double *P = S.P[cur];
     Nb q = nbrs(x, y, S.nx, S.ny);
-    float Pc[2] = {P[q.c], P[N + q.c]}, Pe[2] = {P[q.e], P[N + q.e]}, Pw[2] = {P[q.w], P[N + q.w]};
-    float Pn[2] = {P[q.n], P[N + q.n]}, Ps[2] = {P[q.s], P[N + q.s]};
+    double Pc[2] = {P[q.c], P[N + q.c]}, Pe[2] = {P[q.e], P[N + q.e]}, Pw[2] = {P[q.w], P[N + q.w]};
+    double Pn[2] = {P[q.n], P[N + q.n]}, Ps[2] = {P[q.s], P[N + q.s]};
     float E[4];
     ericksen(S, Pc, Pe, Pw, Pn, Ps, E);
     for (int k = 0; k < 4; ++k) S.sE[k * N + q.c] = E[k];
@@ -556,8 +570,8 @@ __device__ __forceinline__ void gather3(const float *f, size_t N, const Nb &q, f
         Xs[k] = f[k * N + q.s];
     }
 }
-__device__ __forceinline__ void gather2(const float *f, size_t N, const Nb &q, float X[2], float Xe[2], float Xw[2],
-                                        float Xn[2], float Xs[2]) {
+__device__ __forceinline__ void gather2(const double *f, size_t N, const Nb &q, double X[2], double Xe[2], double Xw[2],
+                                        double Xn[2], double Xs[2]) {
     for (int k = 0; k < 2; ++k) {
         X[k] = f[k * N + q.c];
         Xe[k] = f[k * N + q.e];
@@ -578,13 +592,13 @@ __global__ __launch_bounds__(256) void k_mp_pred(const SimDev *__restrict__ sims
     float ux = S.v[q.c], uy = S.v[N + q.c];
     float X[3], Xe[3], Xw[3], Xn[3], Xs[3], Rs[3];
     gather3(S.sig[cur], N, q, X, Xe, Xw, Xn, Xs);
-    float Y[2], Ye[2], Yw[2], Yn[2], Ys[2], Rp[2];
+    double Y[2], Ye[2], Yw[2], Yn[2], Ys[2], Rp[2];
     gather2(S.P[cur], N, q, Y, Ye, Yw, Yn, Ys);
-    Stiff k = stiffness(S, Y[0], Y[1]);
+    Stiff k = stiffness(S, (float)Y[0], (float)Y[1]);
     rhs_sigma(S, k, g, ux, uy, X, Xe, Xw, Xn, Xs, Rs);
     rhs_P(S, g, ux, uy, Y, Ye, Yw, Yn, Ys, Rp);
-    for (int c = 0; c < 3; ++c) S.sp[c * N + q.c] = X[c] + Rs[c];
-    for (int c = 0; c < 2; ++c) S.sp[(3 + c) * N + q.c] = Y[c] + Rp[c];
+    for (int c = 0; c < 3; ++c) S.sps[c * N + q.c] = X[c] + Rs[c];
+    for (int c = 0; c < 2; ++c) S.spp[c * N + q.c] = Y[c] + Rp[c];
 }
 
 __global__ __launch_bounds__(256) void k_mp_corr(const SimDev *__restrict__ sims, const SiteBlock *__restrict__ blk,
@@ -596,18 +610,19 @@ __global__ __launch_bounds__(256) void k_mp_corr(const SimDev *__restrict__ sims
     Nb q = nbrs(x, y, S.nx, S.ny);
     Grad g = grad_at(S, q);
     float ux = S.v[q.c], uy = S.v[N + q.c];
-    const float *P = S.P[cur];
-    Stiff k = stiffness(S, P[q.c], P[N + q.c]);
+    const double *P = S.P[cur];
+    Stiff k = stiffness(S, (float)P[q.c], (float)P[N + q.c]);
     float X[3], Xe[3], Xw[3], Xn[3], Xs[3], Rs[3];
-    gather3(S.sp, N, q, X, Xe, Xw, Xn, Xs);
-    float Y[2], Ye[2], Yw[2], Yn[2], Ys[2], Rp[2];
-    gather2(S.sp + 3 * N, N, q, Y, Ye, Yw, Yn, Ys);
+    gather3(S.sps, N, q, X, Xe, Xw, Xn, Xs);
+    double Y[2], Ye[2], Yw[2], Yn[2], Ys[2], Rp[2];
+    gather2(S.spp, N, q, Y, Ye, Yw, Yn, Ys);
     rhs_sigma(S, k, g, ux, uy, X, Xe, Xw, Xn, Xs, Rs);
     rhs_P(S, g, ux, uy, Y, Ye, Yw, Yn, Ys, Rp);
     const float *sg = S.sig[cur];
-    float *so = S.sig[cur ^ 1], *Po = S.P[cur ^ 1];
+    float *so = S.sig[cur ^ 1];
+    double *Po = S.P[cur ^ 1];
     for (int c = 0; c < 3; ++c) so[c * N + q.c] = 0.5f * ((sg[c * N + q.c] + X[c]) + Rs[c]);
-    for (int c = 0; c < 2; ++c) Po[c * N + q.c] = 0.5f * ((P[c * N + q.c] + Y[c]) + Rp[c]);
+    for (int c = 0; c < 2; ++c) Po[c * N + q.c] = 0.5 * ((P[c * N + q.c] + Y[c]) + Rp[c]);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -629,15 +644,16 @@ __global__ __launch_bounds__(256) void k_readout(const SimDev *__restrict__ sims
     pull_pops<HT>(S, reinterpret_cast<const HT *>(S.h[cur]), x, y, d);
     float drho, ux, uy;
     collide(d, Fx, Fy, S.omega, S.guo, drho, ux, uy);
-    const float *sg = S.sig[cur], *P = S.P[cur];
+    const float *sg = S.sig[cur];
+    const double *P = S.P[cur];
     out[0 * N + q.c] = drho;
     out[1 * N + q.c] = ux;
     out[2 * N + q.c] = uy;
     out[3 * N + q.c] = sg[q.c];
     out[4 * N + q.c] = sg[N + q.c];
     out[5 * N + q.c] = sg[2 * N + q.c];
-    out[6 * N + q.c] = P[q.c];
-    out[7 * N + q.c] = P[N + q.c];
+    out[6 * N + q.c] = (float)P[q.c];
+    out[7 * N + q.c] = (float)P[N + q.c];
     out[8 * N + q.c] = fpx;
     out[9 * N + q.c] = fpy;
 }

@@ -47,7 +47,8 @@ def test_initial_state_matches(kernel):
     say(f"case initial-state kernel={kernel} 40x36 seed=41")
     g = lb.Sim(w, lb.make_options(kernel=kernel))
     r = oracle_sim(w.sims[0])
-    compare(g, r, tol=1e-6, node_tol=1e-12)
+    # FP32 rounding of alpha + beta|P|^2 (about 0 at the equilibrium magnitude) bounds this at ~1e-5
+    compare(g, r, tol=2e-5, node_tol=1e-12)
 
 
 @pytest.mark.parametrize("kernel", [0, 1], ids=["fused", "multipass"])
