@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Benchmark of the coupled viscoelastic IB-LB step on one MI355X.
+
+One "step" is one full coupled update of every lattice site (fused field kernel + body update).
+Prints ONE JSON line with MLUPS (whole job), the roofline of the dominant kernel (the fused field
+kernel, HBM-bound, algorithmic bytes / launch duration measured with HIP events on the library's
+stream) and the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+Default workload: 512 x 512 periodic, one body R = 16 with 100 nodes, FP32 populations, directors
+at 30 deg + N(0, 0.1 rad) (the single-simulation FP32 configuration).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS and % HBM roofline per coupled step; surrogate-vs-LB speedup at 2% error"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bytes_per_site(precision: int) -> int:
+    """Algorithmic HBM bytes per site update: every state value read once and written once.
+    Populations 9 x (4 B FP32 | 2 B FP16), stress 3 x 4 B, polarization 2 x 8 B (FP64)."""
+    pop = 9 * (2 if precision == 1 else 4)
+    return 2 * (pop + 3 * 4 + 2 * 8)
+
+
+def workload(name: str, steps: int):
+    from paper_2209_14889_amd import workload as wl
+    if name == "c2":
+        w = wl.c2(steps=steps)
+        desc = "D2Q9 512x512 periodic, 1 body R=16 N=100, pull 5e-5, directors 30deg+N(0,0.1), relax 200, D=0.02"
+        return w, desc, 0
+    if name == "c3":
+        w = wl.c3(steps=steps)
+        desc = "D2Q9 2048x2048 periodic, 8 bodies R 12-24, FP16 population offsets (x2^10), FP32 math"
+        return w, desc, 1
+    if name == "c3fp32":
+        w = wl.c3(steps=steps)
+        desc = "D2Q9 2048x2048 periodic, 8 bodies R 12-24, FP32 populations"
+        return w, desc, 0
+    if name == "c1":
+        w = wl.c1(steps=steps)
+        return w, "D2Q9 64x64 periodic, 1 body R=6 N=40, random directors", 0
+    if name == "c4":
+        w = wl.c4(steps=steps)
+        return w, "256-simulation ensemble, sizes {64..512}^2, one body each", 0
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(w, name: str, budget_s: float = 15.0):
+    """FP64 oracle on the host: the full coupled step on the workload's first simulation for as
+    many steps as fit in about budget_s seconds (at least 2)."""
+    import oracle
+    cores = min(os.cpu_count() or 1, 16)
+    oracle.set_threads(cores)
+    s = w.sims[0]
+    p = s.params
+    bodies = [oracle.Body(R=b.R.copy(), k_spring=b.k_spring, eps_angle=b.eps_angle, l_eq=b.l_eq, pull=b.pull,
+                          t_on=b.t_on, t_off=b.t_off, width=b.width) for b in s.bodies]
+    sim = oracle.Sim(dict(nx=s.nx, ny=s.ny, tau=p["tau"], Kx=p["Kx"], eta_p=p["eta_p"], D_p=p["D_p"], xi=p["xi"],
+                          alpha=p["alpha"], beta=p["beta"], kappa=p["kappa"], Gamma=p["Gamma"],
+                          P_clamp=p["P_clamp"], ericksen=p["ericksen"]), bodies=bodies, P=s.P0.copy())
+    t0 = time.perf_counter()
+    sim.run(1)
+    dt1 = time.perf_counter() - t0
+    n = max(2, min(200, int(budget_s / max(dt1, 1e-6))))
+    t0 = time.perf_counter()
+    sim.run(n)
+    dt = time.perf_counter() - t0
+    sites = s.nx * s.ny
+    return {"value": round(sites * n / dt / 1e6, 4), "unit": "MLUPS", "cores": int(oracle.get_threads()),
+            "kind": "oracle", "sample": f"{name}: first simulation {s.nx}x{s.ny}, {n} coupled steps after 1 warm-up step"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--kernel", type=int, default=0, help="0 fused, 1 multi-pass")
+    ap.add_argument("--graph-chunk", type=int, default=100)
+    ap.add_argument("--seg-rows", type=int, default=0)
+    ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--timing-steps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no multi-GPU "
+              "path; independent simulations shard across GPUs with no exchange and one large lattice would "
+              "use slab halos, neither of which is built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2209_14889_amd import lb
+
+    w, desc, precision = workload(args.workload, args.steps)
+    sites = w.sites
+    log(f"bench: workload {args.workload} ({desc}), {sites} sites, warmup {args.warmup}, steps {args.steps}")
+
+    opt = lb.make_options(precision=precision, kernel=args.kernel, graph_chunk=args.graph_chunk,
+                          seg_rows=args.seg_rows, fused_threads=args.threads)
+    sim = lb.Sim(w, opt)
+    sim.step(args.warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    mlups = sites * args.steps / dt / 1e6
+    log(f"bench: {args.steps} steps in {dt:.4f} s -> {mlups:.1f} MLUPS")
+    sim.close()
+
+    # roofline of the dominant kernel: HIP events around every field-kernel launch on the
+    # library's stream (plain launches, same kernel and launch configuration)
+    topt = lb.make_options(precision=precision, kernel=args.kernel, timing=1, seg_rows=args.seg_rows,
+                           fused_threads=args.threads)
+    tsim = lb.Sim(w, topt)
+    tsim.step(20)
+    tsim.timing(reset=True)
+    tsim.step(args.timing_steps)
+    tm = tsim.timing()
+    tsim.close()
+    avg_ms = tm["field_ms"] / max(1, tm["field_launches"])
+    ib_ms = tm["ib_ms"] / max(1, tm["ib_launches"]) if tm["ib_launches"] else 0.0
+    bps = bytes_per_site(precision)
+    achieved = bps * sites / (avg_ms * 1e-3) / 1e9
+    log(f"bench: field kernel {avg_ms * 1e3:.2f} us/launch, body kernel {ib_ms * 1e3:.2f} us/launch, "
+        f"{achieved:.0f} GB/s algorithmic")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: timing the FP64 oracle on the host")
+        cpu = cpu_baseline(w, args.workload)
+        log(f"bench: oracle {cpu['value']} MLUPS on {cpu['cores']} threads")
+
+    line = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16-storage/f32" if precision == 1 else "f32 (P in f64)",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "sites": sites, "kernel": "fused" if args.kernel == 0 else "multipass",
+                   "graph_chunk": args.graph_chunk},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_fused", "bytes_per_site": bps, "launch_us": round(avg_ms * 1e3, 3)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
