@@ -6,8 +6,9 @@ Prints ONE JSON line with MLUPS (whole job), the roofline of the dominant kernel
 kernel, HBM-bound, algorithmic bytes / launch duration measured with HIP events on the library's
 stream) and the FP64 CPU oracle timed on a bounded sample of the same workload.
 
-Default workload: 512 x 512 periodic, one body R = 16 with 100 nodes, FP32 populations, directors
-at 30 deg + N(0, 0.1 rad) (the single-simulation FP32 configuration).
+Default workload: the HBM-bound precision form, 2048 x 2048 periodic with 8 bodies (radius 12-24)
+and FP16 population offsets (FP32 arithmetic).  --workload c2 runs the 512 x 512 single FP32
+simulation (cache-resident), c4 the 256-simulation ensemble.
 """
 from __future__ import annotations
 
@@ -90,13 +91,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c3")
     ap.add_argument("--kernel", type=int, default=0, help="0 fused, 1 multi-pass")
     ap.add_argument("--graph-chunk", type=int, default=100)
     ap.add_argument("--seg-rows", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--timing-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no multi-GPU "
@@ -112,8 +114,11 @@ def main():
     log(f"bench: workload {args.workload} ({desc}), {sites} sites, warmup {args.warmup}, steps {args.steps}")
 
     opt = lb.make_options(precision=precision, kernel=args.kernel, graph_chunk=args.graph_chunk,
-                          seg_rows=args.seg_rows, fused_threads=args.threads)
+                          seg_rows=args.seg_rows, fused_threads=args.threads,
+                          autotune=0 if (args.no_autotune or args.seg_rows) else 1)
     sim = lb.Sim(w, opt)
+    shape = sim.launch_shape()
+    log(f"bench: fused launch shape {shape}")
     sim.step(args.warmup)
     sim.sync()
     torch.cuda.synchronize()
@@ -128,8 +133,8 @@ def main():
 
     # roofline of the dominant kernel: HIP events around every field-kernel launch on the
     # library's stream (plain launches, same kernel and launch configuration)
-    topt = lb.make_options(precision=precision, kernel=args.kernel, timing=1, seg_rows=args.seg_rows,
-                           fused_threads=args.threads)
+    topt = lb.make_options(precision=precision, kernel=args.kernel, timing=1, seg_rows=shape["seg_rows"],
+                           fused_threads=shape["threads"])
     tsim = lb.Sim(w, topt)
     tsim.step(20)
     tsim.timing(reset=True)
@@ -162,8 +167,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f16-storage/f32" if precision == 1 else "f32 (P in f64)",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {desc}", "sites": sites, "kernel": "fused" if args.kernel == 0 else "multipass",
-                   "graph_chunk": args.graph_chunk},
+        "config": {"workload": f"{args.workload}: {desc}", "sites": sites,
+                   "kernel": "fused" if args.kernel == 0 else "multipass", "graph_chunk": args.graph_chunk,
+                   "threads": shape["threads"], "seg_rows": shape["seg_rows"], "work_items": shape["n_items"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_fused", "bytes_per_site": bps, "launch_us": round(avg_ms * 1e3, 3)},

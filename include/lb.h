@@ -58,7 +58,7 @@ typedef struct {
 
 /* One simulation on a periodic nx x ny lattice. */
 typedef struct {
-    int32_t nx, ny;             /* 8 .. 16384 each */
+    int32_t nx, ny;             /* 8 .. 16384 each, nx*ny <= 1e8 */
     double tau;                 /* BGK relaxation time (eqBGK), > 0.5 */
     double Kx[4];               /* K1111, K1122, K2222, K1212 of the aligned stiffness (eqKmatrix) */
     double eta_p;               /* polymer viscosity (eqStiffCons), > 0 (may be +inf) */
@@ -84,7 +84,9 @@ typedef struct {
     int32_t seg_rows;           /* rows per fused work item; 0 = tuned default */
     int32_t fused_threads;      /* fused work-group size: 128 or 256 (strip of 120 or 248
                                    columns); 0 = chosen from the lattice width */
-    int32_t reserved[4];
+    int32_t autotune;           /* 1: time candidate (work-group size, rows per item) pairs on the
+                                   live state in lb_create and keep the fastest; 0: cost model */
+    int32_t reserved[3];
 } lb_options;
 
 /* Bytes of device memory lb_create needs for these simulations (arena for all state, tables,
@@ -143,6 +145,10 @@ int lb_time(lb_handle *h, int64_t *t);
  * the same for the immersed-boundary kernel; counters reset when reset != 0.  Synchronous. */
 int lb_timing(lb_handle *h, double *field_ms, int64_t *field_launches, double *ib_ms,
               int64_t *ib_launches, int32_t reset);
+
+/* Fused-kernel launch shape in use: work-group size, rows per work item, number of work items,
+ * and (after autotuning) the measured milliseconds per launch of the chosen shape (else 0). */
+int lb_launch_shape(lb_handle *h, int32_t *threads, int32_t *seg_rows, int32_t *n_items, double *tuned_ms);
 
 /* Release the handle's host resources (and its stream if the library created it). */
 int lb_destroy(lb_handle *h);

@@ -173,6 +173,7 @@ struct Plan {
 
 struct Opt {
     int precision = 0, shift = kDefaultShift, watchdog = 0, chunk = 0, kernel = 0, timing = 0, seg = 0, threads = 0;
+    int autotune = 0;
 };
 
 Opt read_opt(const lb_options *o) {
@@ -186,6 +187,7 @@ Opt read_opt(const lb_options *o) {
     r.timing = o->timing;
     r.seg = o->seg_rows;
     r.threads = o->fused_threads;
+    r.autotune = o->autotune;
     return r;
 }
 
@@ -215,6 +217,7 @@ int validate(const lb_sim_params *sims, int n_sims, const Opt &o) {
     for (int s = 0; s < n_sims; ++s) {
         const lb_sim_params &p = sims[s];
         if (p.nx < 8 || p.ny < 8 || p.nx > 16384 || p.ny > 16384) return fail(LB_EINVAL, "sim %d: lattice size out of range", s);
+        if ((long long)p.nx * p.ny > 100000000LL) return fail(LB_EINVAL, "sim %d: more than 1e8 lattice sites", s);
         if (!(p.tau > 0.5)) return fail(LB_EINVAL, "sim %d: tau must exceed 0.5", s);
         if (!(p.D_p >= 0.0) || !(8.0 * p.D_p < 2.0)) return fail(LB_EINVAL, "sim %d: need 0 <= D_p and 8 D_p < 2", s);
         if (!(p.eta_p > 0.0)) return fail(LB_EINVAL, "sim %d: eta_p must be positive", s);
@@ -292,7 +295,7 @@ Plan make_plan(const lb_sim_params *sims, int n_sims, const Opt &o) {
             bp.oR0 = a.take(16 * (size_t)bp.n);
             bp.oR1 = a.take(16 * (size_t)bp.n);
             bp.oF = a.take(16 * (size_t)bp.n);
-            bp.oOrigin = a.take(4 * sizeof(int));
+            bp.oOrigin = a.take(8 * sizeof(int));
             bp.oFib = a.take(2 * (size_t)bp.ps * bp.ps * 4);
             bp.oVib = a.take(2 * (size_t)bp.ps * bp.ps * 4);
             for (int q = 0; q < bp.nside * bp.nside; ++q) pl.ib_blk.push_back(make_int2((int)pl.bodies.size(), q));
@@ -300,32 +303,14 @@ Plan make_plan(const lb_sim_params *sims, int n_sims, const Opt &o) {
         }
         pl.sims.push_back(sp);
     }
-    // fused work items: strips of <= T-8 columns, segments of seg rows
-    long strip_rows = 0;
+    // fused work items are built in lb_create (they depend on the device); reserve room for
+    // the shortest segments any choice may use
+    size_t max_items = 0;
     for (int s = 0; s < n_sims; ++s) {
-        int W = pl.T - 2 * kHalo;
-        int ns = (sims[s].nx + W - 1) / W;
-        strip_rows += (long)ns * sims[s].ny;
+        int W = 128 - 2 * kHalo;
+        max_items += (size_t)((sims[s].nx + W - 1) / W) * (size_t)((sims[s].ny + 3) / 4);
     }
-    int seg = o.seg;
-    if (seg <= 0) {
-        long target = 2048;
-        seg = (int)std::max(8L, std::min(64L, (strip_rows + target - 1) / target));
-        seg = (seg + 3) & ~3;
-    }
-    for (int s = 0; s < n_sims; ++s) {
-        int W = pl.T - 2 * kHalo;
-        int nx = sims[s].nx, ny = sims[s].ny;
-        int ns = (nx + W - 1) / W;
-        int ng = (ny + seg - 1) / seg;
-        for (int g = 0; g < ng; ++g) {
-            int y0 = (int)((long)g * ny / ng), y1 = (int)((long)(g + 1) * ny / ng);
-            for (int k = 0; k < ns; ++k) {
-                int x0 = (int)((long)k * nx / ns), x1 = (int)((long)(k + 1) * nx / ns);
-                pl.items.push_back(WorkItem{s, x0, y0, x1 - x0, y1 - y0, 0, 0, 0});
-            }
-        }
-    }
+    pl.items.resize(max_items);
     pl.oItems = a.take(sizeof(WorkItem) * pl.items.size());
     pl.oIbBlk = a.take(sizeof(int2) * std::max<size_t>(1, pl.ib_blk.size()));
     pl.oSiteBlk = a.take(sizeof(SiteBlock) * pl.site_blk.size());
@@ -337,6 +322,42 @@ Plan make_plan(const lb_sim_params *sims, int n_sims, const Opt &o) {
     pl.oStage = a.take(10 * maxN * 4);
     pl.bytes = a.off + 256;
     return pl;
+}
+
+// strips of at most T-8 columns (nearly equal widths) and segments of about seg rows
+std::vector<WorkItem> build_items(const std::vector<SimPlan> &sims, int T, int seg) {
+    std::vector<WorkItem> items;
+    const int W = T - 2 * kHalo;
+    for (size_t s = 0; s < sims.size(); ++s) {
+        int nx = sims[s].nx, ny = sims[s].ny;
+        int ns = (nx + W - 1) / W;
+        int ng = std::max(1, (ny + seg - 1) / seg);
+        for (int g = 0; g < ng; ++g) {
+            int y0 = (int)((long)g * ny / ng), y1 = (int)((long)(g + 1) * ny / ng);
+            for (int k = 0; k < ns; ++k) {
+                int x0 = (int)((long)k * nx / ns), x1 = (int)((long)(k + 1) * nx / ns);
+                items.push_back(WorkItem{(int)s, x0, y0, x1 - x0, y1 - y0, 0, 0, 0});
+            }
+        }
+    }
+    return items;
+}
+
+// cost model of one fused launch: work items run in rounds of `slots` resident work-groups and
+// an item of seg rows takes seg + 8 row iterations (the pipeline fill)
+int model_seg(const std::vector<SimPlan> &sims, int T, int slots) {
+    int best = 8;
+    double best_cost = 1e300;
+    for (int seg = 4; seg <= 128; ++seg) {
+        size_t items = build_items(sims, T, seg).size();
+        double rounds = std::ceil((double)items / slots);
+        double cost = rounds * (seg + 8) + 1e-3 * seg;   // ties: shorter segments
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = seg;
+        }
+    }
+    return best;
 }
 
 }  // namespace
@@ -366,6 +387,10 @@ struct lb_handle {
     int64_t t = 0;
     int cur = 0;
     int fused_grid = 0;
+    int fused_T = 256;
+    int fused_seg = 0;
+    int n_items = 0;
+    float tuned_ms = 0.f;
     // graph replay
     hipGraphExec_t gexec = nullptr;
     int gsteps = 0;
@@ -436,8 +461,8 @@ int launch_step(lb_handle *h, bool timed) {
         HIPCHK(hipEventRecord(a, h->stream));
     }
     if (h->opt.kernel == 0) {
-        HIPCHK(launch_fused(h->plan.T, fp16, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
-                            (int)h->plan.items.size(), h->cur, h->d_t));
+        HIPCHK(launch_fused(h->fused_T, fp16, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
+                            h->n_items, h->cur, h->d_t));
     } else {
         HIPCHK(launch_multipass(fp16, (int)h->plan.site_blk.size(), h->stream, h->d_sims, h->d_bodies, h->d_site,
                                 h->cur, h->d_t));
@@ -468,6 +493,93 @@ int launch_step(lb_handle *h, bool timed) {
         if (rc) return rc;
     }
     return LB_OK;
+}
+
+int upload_items(lb_handle *h, int T, int seg) {
+    std::vector<WorkItem> items = build_items(h->plan.sims, T, seg);
+    if (items.size() > h->plan.items.size()) return fail(LB_EINVAL, "internal: work-item table overflow");
+    HIPCHK(hipMemcpyAsync(h->d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->fused_T = T;
+    h->fused_seg = seg;
+    h->n_items = (int)items.size();
+    h->fused_grid = h->n_items;
+    return LB_OK;
+}
+
+// Work-group size and segment length of the fused kernel.  Default: the cost model with the
+// device's compute units and the kernel's occupancy.  With opt.autotune, every candidate pair
+// (T, seg) near the model's choices is timed with HIP events on the live state: a launch reads
+// buffer `cur` and writes the other one, so repeating it without flipping the parity changes
+// nothing (the step counter it advances is restored afterwards).
+int choose_fused_config(lb_handle *h) {
+    if (h->opt.kernel != 0) return LB_OK;
+    const bool fp16 = h->opt.precision == 1;
+    int dev = 0, cus = 256;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    auto model_T = [&]() {
+        if (h->opt.threads) return h->opt.threads;
+        int mx = 0;
+        for (const auto &sp : h->plan.sims) mx = std::max(mx, sp.nx);
+        return mx <= 120 ? 128 : 256;
+    };
+    if (!h->opt.autotune) {
+        int T = model_T();
+        int seg = h->opt.seg ? h->opt.seg : model_seg(h->plan.sims, T, cus * fused_blocks_per_cu(T, fp16));
+        return upload_items(h, T, seg);
+    }
+    std::vector<std::pair<int, int>> cand;
+    for (int T : {128, 256}) {
+        if (h->opt.threads && T != h->opt.threads) continue;
+        int slots = cus * fused_blocks_per_cu(T, fp16);
+        int m = model_seg(h->plan.sims, T, slots);
+        for (int seg : {m, std::max(4, m / 2), m * 2, m + 4, std::max(4, m - 4)})
+            if (std::find(cand.begin(), cand.end(), std::make_pair(T, seg)) == cand.end()) cand.emplace_back(T, seg);
+    }
+    int t_saved = 0;
+    HIPCHK(hipMemcpy(&t_saved, h->d_t, sizeof(int), hipMemcpyDeviceToHost));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    // warm the clocks with the first candidate, then time every candidate in two passes and
+    // keep each one's best pass (clock ramps and neighbours on the device add noise)
+    {
+        int rc = upload_items(h, cand.front().first, cand.front().second);
+        if (rc) return rc;
+        for (int r = 0; r < 30; ++r)
+            HIPCHK(launch_fused(cand.front().first, fp16, h->fused_grid, h->stream, h->d_sims, h->d_bodies,
+                                h->d_items, h->n_items, h->cur, h->d_t));
+    }
+    std::vector<float> tbest(cand.size(), 1e30f);
+    for (int pass = 0; pass < 2; ++pass) {
+        for (size_t ci = 0; ci < cand.size(); ++ci) {
+            const auto c = cand[ci];
+            int rc = upload_items(h, c.first, c.second);
+            if (rc) return rc;
+            HIPCHK(launch_fused(c.first, fp16, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
+                                h->n_items, h->cur, h->d_t));
+            HIPCHK(hipEventRecord(e0, h->stream));
+            for (int r = 0; r < 8; ++r)
+                HIPCHK(launch_fused(c.first, fp16, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
+                                    h->n_items, h->cur, h->d_t));
+            HIPCHK(hipEventRecord(e1, h->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            tbest[ci] = std::min(tbest[ci], ms / 8.0f);
+        }
+    }
+    size_t bi = 0;
+    for (size_t ci = 1; ci < cand.size(); ++ci)
+        if (tbest[ci] < tbest[bi]) bi = ci;
+    const std::pair<int, int> pick = cand[bi];
+    const float best = tbest[bi];
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(hipMemcpy(h->d_t, &t_saved, sizeof(int), hipMemcpyHostToDevice));
+    h->tuned_ms = best;
+    return upload_items(h, pick.first, pick.second);
 }
 
 int run_watchdog(lb_handle *h) {
@@ -695,7 +807,6 @@ static int create_impl(const lb_sim_params *sims, int n_sims, const lb_options *
     HIPCHK(hipMemcpyAsync(h->d_sims, h->hs.data(), sizeof(SimDev) * n_sims, hipMemcpyHostToDevice, h->stream));
     if (!h->hb.empty())
         HIPCHK(hipMemcpyAsync(h->d_bodies, h->hb.data(), sizeof(BodyDev) * h->hb.size(), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(hipMemcpyAsync(h->d_items, pl.items.data(), sizeof(WorkItem) * pl.items.size(), hipMemcpyHostToDevice, h->stream));
     if (!pl.ib_blk.empty())
         HIPCHK(hipMemcpyAsync(h->d_ib, pl.ib_blk.data(), sizeof(int2) * pl.ib_blk.size(), hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipMemcpyAsync(h->d_site, pl.site_blk.data(), sizeof(SiteBlock) * pl.site_blk.size(), hipMemcpyHostToDevice,
@@ -704,7 +815,8 @@ static int create_impl(const lb_sim_params *sims, int n_sims, const lb_options *
     HIPCHK(hipMemcpyAsync(h->d_t, zero, sizeof(int), hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipMemcpyAsync(h->d_status, zero, sizeof(int), hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
-    h->fused_grid = (int)pl.items.size();
+    rc = choose_fused_config(h.get());
+    if (rc) return rc;
 
     // initial body forces spread onto their patches
     if (!pl.ib_blk.empty())
@@ -893,6 +1005,15 @@ int lb_timing(lb_handle *h, double *field_ms, int64_t *field_n, double *ib_ms, i
         h->field_ms = h->ib_ms = 0;
         h->field_n = h->ib_n = 0;
     }
+    return LB_OK;
+}
+
+int lb_launch_shape(lb_handle *h, int32_t *threads, int32_t *seg_rows, int32_t *n_items, double *tuned_ms) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (threads) *threads = h->fused_T;
+    if (seg_rows) *seg_rows = h->fused_seg;
+    if (n_items) *n_items = h->n_items;
+    if (tuned_ms) *tuned_ms = h->tuned_ms;
     return LB_OK;
 }
 

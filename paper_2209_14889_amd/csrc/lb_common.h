@@ -46,7 +46,8 @@ struct BodyDev {
     double k, eps, leq, fx, fy, t_on, t_off, width;
     double *R[2];                   // node positions by step parity, interleaved x, y
     double *fnode;                  // node forces at the current time (2n)
-    int *origin;                    // patch origin by step parity: [parity][2]
+    int *origin;                    // patch origin by step parity: [parity][4] = unwrapped x, y
+                                    // (node coordinates), then x mod nx, y mod ny
     float *fib;                     // spread force patch: 2 planes ps*ps
     float *vib;                     // fluid velocity patch: 2 planes ps*ps
 };

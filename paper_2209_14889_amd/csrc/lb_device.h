@@ -10,6 +10,15 @@
 
 namespace lbk {
 
+// global address space: loads and stores through these pointers compile to global_* instructions
+// (flat ones would also count against the LDS wait counter and serialise the row prefetch)
+#define LBK_GLOBAL __attribute__((address_space(1)))
+
+template <typename T> __device__ __forceinline__ const LBK_GLOBAL T *gptr(const T *p) {
+    return (const LBK_GLOBAL T *)p;
+}
+template <typename T> __device__ __forceinline__ LBK_GLOBAL T *gptr(T *p) { return (LBK_GLOBAL T *)p; }
+
 // D2Q9: rest, +x, +y, -x, -y, (+,+), (-,+), (-,-), (+,-)
 __device__ constexpr int kCX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __device__ constexpr int kCY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
@@ -23,9 +32,21 @@ __device__ __forceinline__ int wrapi(int i, int n) {
 
 // ---- population storage -----------------------------------------------------------------
 template <typename HT> struct Pop;
+// every state array of one simulation is < 4 GiB (lb_create limits a lattice to 1e8 sites), so
+// an unsigned 32-bit element index from a uniform base addresses it
+// byte offset of element i, kept in 32 bits so the address is scalar base + 32-bit vector offset
+template <typename T> __device__ __forceinline__ const LBK_GLOBAL T *at32(const T *base, unsigned i) {
+    return (const LBK_GLOBAL T *)((const LBK_GLOBAL char *)base + i * (unsigned)sizeof(T));
+}
+template <typename T> __device__ __forceinline__ LBK_GLOBAL T *at32(T *base, unsigned i) {
+    return (LBK_GLOBAL T *)((LBK_GLOBAL char *)base + i * (unsigned)sizeof(T));
+}
+
 template <> struct Pop<float> {
     static __device__ __forceinline__ float load(const float *p, size_t i, float) { return p[i]; }
     static __device__ __forceinline__ void store(float *p, size_t i, float v, float) { p[i] = v; }
+    static __device__ __forceinline__ float ld(const float *p, unsigned i, float) { return *at32(p, i); }
+    static __device__ __forceinline__ void st(float *p, unsigned i, float v, float) { *at32(p, i) = v; }
 };
 template <> struct Pop<__half> {
     static __device__ __forceinline__ float load(const __half *p, size_t i, float inv_scale) {
@@ -33,6 +54,12 @@ template <> struct Pop<__half> {
     }
     static __device__ __forceinline__ void store(__half *p, size_t i, float v, float scale) {
         p[i] = __float2half_rn(v * scale);
+    }
+    static __device__ __forceinline__ float ld(const __half *p, unsigned i, float inv_scale) {
+        return __half2float(__ushort_as_half(*at32(reinterpret_cast<const unsigned short *>(p), i))) * inv_scale;
+    }
+    static __device__ __forceinline__ void st(__half *p, unsigned i, float v, float scale) {
+        *at32(reinterpret_cast<unsigned short *>(p), i) = __half_as_ushort(__float2half_rn(v * scale));
     }
 };
 
@@ -78,9 +105,9 @@ __device__ __forceinline__ Stiff stiffness(const SimDev &S, float Px, float Py) 
         float u = s * S.inv_ds;
         int i = min((int)u, kTab - 1);
         float fr = u - (float)i;
-        float4 t = S.tab[i];
-        A2 = fmaf(fr, t.y, t.x);
-        A4 = fmaf(fr, t.w, t.z);
+        const LBK_GLOBAL float *t = (const LBK_GLOBAL float *)S.tab + 4 * i;
+        A2 = fmaf(fr, t[1], t[0]);
+        A4 = fmaf(fr, t[3], t[2]);
     } else {
         float r = S.smax / s;
         A2 = S.A2max * r;
@@ -190,17 +217,23 @@ __device__ __forceinline__ void ericksen(const SimDev &S, const double P[2], con
     E[3] = (float)(xi * P[1] * hy - kap * (dyPx * dyPx + dyPy * dyPy));
 }
 
+// (x - o) mod n for |x - o| < 2n, without an integer division
+__device__ __forceinline__ int wrap_near(int d, int n) {
+    d = d < 0 ? d + n : d;
+    return d >= n ? d - n : d;
+}
+
 // immersed-boundary force at lattice site (x, y) from the bodies' spread-force patches
 __device__ __forceinline__ void ib_force(const SimDev &S, const BodyDev *bodies, int parity, int x, int y,
                                          float &Fx, float &Fy) {
     for (int b = 0; b < S.nb; ++b) {
         const BodyDev &B = bodies[S.b0 + b];
-        int ox = B.origin[2 * parity], oy = B.origin[2 * parity + 1];
-        int px = wrapi(x - ox, S.nx), py = wrapi(y - oy, S.ny);
+        int px = wrap_near(x - gptr(B.origin)[4 * parity + 2], S.nx);
+        int py = wrap_near(y - gptr(B.origin)[4 * parity + 3], S.ny);
         if (px < B.ps && py < B.ps) {
-            size_t i = (size_t)py * B.ps + px;
-            Fx += B.fib[i];
-            Fy += B.fib[(size_t)B.ps * B.ps + i];
+            unsigned i = (unsigned)(py * B.ps + px);
+            Fx += gptr(B.fib)[i];
+            Fy += gptr(B.fib)[(unsigned)(B.ps * B.ps) + i];
         }
     }
 }
@@ -210,14 +243,19 @@ __device__ __forceinline__ void ib_store_v(const SimDev &S, const BodyDev *bodie
                                            float ux, float uy) {
     for (int b = 0; b < S.nb; ++b) {
         const BodyDev &B = bodies[S.b0 + b];
-        int ox = B.origin[2 * parity], oy = B.origin[2 * parity + 1];
-        int px = wrapi(x - ox, S.nx), py = wrapi(y - oy, S.ny);
+        int px = wrap_near(x - gptr(B.origin)[4 * parity + 2], S.nx);
+        int py = wrap_near(y - gptr(B.origin)[4 * parity + 3], S.ny);
         if (px < B.ps && py < B.ps) {
-            size_t i = (size_t)py * B.ps + px;
-            B.vib[i] = ux;
-            B.vib[(size_t)B.ps * B.ps + i] = uy;
+            unsigned i = (unsigned)(py * B.ps + px);
+            gptr(B.vib)[i] = ux;
+            gptr(B.vib)[(unsigned)(B.ps * B.ps) + i] = uy;
         }
     }
 }
+
+// loads and stores at base + idx with a 32-bit byte offset (planes are < 4 GiB), so the address
+// is a scalar base plus one vector register
+template <typename T> __device__ __forceinline__ T ld32(const T *base, unsigned idx) { return *at32(base, idx); }
+template <typename T> __device__ __forceinline__ void st32(T *base, unsigned idx, T v) { *at32(base, idx) = v; }
 
 }  // namespace lbk

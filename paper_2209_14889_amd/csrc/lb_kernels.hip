@@ -24,9 +24,16 @@ namespace lbk {
 // immersed boundary
 // ------------------------------------------------------------------------------------------------
 
-__device__ __forceinline__ double phi_d(double r) {
-    double a = fabs(r);
-    return a < 2.0 ? 0.25 * (1.0 + cos(0.5 * M_PI * r)) : 0.0;
+// the four x (or y) weights phi(R - i), i = floor(R) - 1 .. floor(R) + 2, of the cosine kernel;
+// FP32 is enough for weights of values that are themselves FP32
+__device__ __forceinline__ void phi4(double R, int &i0, float w[4]) {
+    i0 = (int)floor(R) - 1;
+    float fr = (float)(R - (double)i0);   // distance to the first site, in [1, 2)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        float r = fr - (float)k;
+        w[k] = fabsf(r) < 2.0f ? 0.25f * (1.0f + cosf(1.57079632679f * r)) : 0.0f;
+    }
 }
 
 __device__ __forceinline__ double pull_factor(const BodyDev &B, double t) {
@@ -37,26 +44,27 @@ __device__ __forceinline__ double pull_factor(const BodyDev &B, double t) {
 // v at point R from the body's velocity patch (origin ox, oy); flags reads outside the patch
 __device__ __forceinline__ void interp_patch(const BodyDev &B, int ox, int oy, double Rx, double Ry,
                                              double &vx, double &vy, bool &bad) {
-    int ix = (int)floor(Rx) - 1, iy = (int)floor(Ry) - 1;
+    int ix, iy;
+    float wx[4], wy[4];
+    phi4(Rx, ix, wx);
+    phi4(Ry, iy, wy);
     const size_t pp = (size_t)B.ps * B.ps;
     vx = 0.0;
     vy = 0.0;
+    const int px0 = ix - ox, py0 = iy - oy;
+    if (px0 < 0 || py0 < 0 || px0 + 3 >= B.ps || py0 + 3 >= B.ps) {
+        bad = true;
+        return;
+    }
     for (int j = 0; j < 4; ++j) {
-        int Y = iy + j;
-        int py = Y - oy;
-        double wy = phi_d(Ry - Y);
+        double ax = 0.0, ay = 0.0;
+        const size_t q = (size_t)(py0 + j) * B.ps + px0;
         for (int i = 0; i < 4; ++i) {
-            int X = ix + i;
-            int px = X - ox;
-            double w = phi_d(Rx - X) * wy;
-            if (px < 0 || py < 0 || px >= B.ps || py >= B.ps) {
-                bad = true;
-                continue;
-            }
-            size_t q = (size_t)py * B.ps + px;
-            vx += w * (double)B.vib[q];
-            vy += w * (double)B.vib[pp + q];
+            ax += (double)wx[i] * (double)B.vib[q + i];
+            ay += (double)wx[i] * (double)B.vib[pp + q + i];
         }
+        vx += (double)wy[j] * ax;
+        vy += (double)wy[j] * ay;
     }
 }
 
@@ -120,7 +128,8 @@ __global__ __launch_bounds__(256) void k_ib(const SimDev *__restrict__ sims, Bod
                                             int *__restrict__ d_status) {
     __shared__ double2 sR[kMaxNodes];
     __shared__ double2 sF[kMaxNodes];
-    __shared__ int sList[kMaxNodes];
+    __shared__ int4 sCand[kMaxNodes];
+    __shared__ float4 sW[kMaxNodes][2];
     __shared__ double sRed[4][4];
     __shared__ int sCnt[4];
     __shared__ int sTot;
@@ -136,8 +145,8 @@ __global__ __launch_bounds__(256) void k_ib(const SimDev *__restrict__ sims, Bod
     const double2 *Rc = reinterpret_cast<const double2 *>(B.R[cur]);
     int ox = 0, oy = 0;
     if (ADVANCE) {
-        ox = B.origin[2 * cur];
-        oy = B.origin[2 * cur + 1];
+        ox = B.origin[4 * cur];
+        oy = B.origin[4 * cur + 1];
     }
     for (int a = tid; a < n; a += 256) {
         double2 R = Rc[a];
@@ -190,8 +199,10 @@ __global__ __launch_bounds__(256) void k_ib(const SimDev *__restrict__ sims, Bod
             Fn[a] = sF[a];
         }
         if (tid == 0) {
-            B.origin[2 * dst] = nox;
-            B.origin[2 * dst + 1] = noy;
+            B.origin[4 * dst] = nox;
+            B.origin[4 * dst + 1] = noy;
+            B.origin[4 * dst + 2] = wrapi(nox, S.nx);
+            B.origin[4 * dst + 3] = wrapi(noy, S.ny);
         }
     }
 
@@ -213,7 +224,17 @@ __global__ __launch_bounds__(256) void k_ib(const SimDev *__restrict__ sims, Bod
         __syncthreads();
         int off = sTot;
         for (int w = 0; w < wv; ++w) off += sCnt[w];
-        if (flag) sList[off + pre] = a;
+        if (flag) {
+            // candidate: its footprint origin and separable weights, relative to the tile
+            int ix, iy;
+            float wx[4], wy[4];
+            phi4(sR[a].x, ix, wx);
+            phi4(sR[a].y, iy, wy);
+            const int q = off + pre;
+            sCand[q] = make_int4(a, ix - X0, iy - Y0, 0);
+            sW[q][0] = make_float4(wx[0], wx[1], wx[2], wx[3]);
+            sW[q][1] = make_float4(wy[0], wy[1], wy[2], wy[3]);
+        }
         __syncthreads();
         if (tid == 0) sTot += sCnt[0] + sCnt[1] + sCnt[2] + sCnt[3];
         __syncthreads();
@@ -221,15 +242,17 @@ __global__ __launch_bounds__(256) void k_ib(const SimDev *__restrict__ sims, Bod
     const int lx = tid % kPatchTile, ly = tid / kPatchTile;
     const int px = tx * kPatchTile + lx, py = ty * kPatchTile + ly;
     if (px < B.ps && py < B.ps) {
-        const double X = (double)(X0 + lx), Y = (double)(Y0 + ly);
         double fx = 0.0, fy = 0.0;
         for (int q = 0; q < sTot; ++q) {
-            int a = sList[q];
-            double dx = sR[a].x - X, dy = sR[a].y - Y;
-            if (fabs(dx) < 2.0 && fabs(dy) < 2.0) {
-                double w = phi_d(dx) * phi_d(dy);
-                fx += sF[a].x * w;
-                fy += sF[a].y * w;
+            const int4 cq = sCand[q];
+            const int i = lx - cq.y, jj = ly - cq.z;
+            if ((unsigned)i < 4u && (unsigned)jj < 4u) {
+                const float4 wxv = sW[q][0], wyv = sW[q][1];
+                const float wxs = i == 0 ? wxv.x : i == 1 ? wxv.y : i == 2 ? wxv.z : wxv.w;
+                const float wys = jj == 0 ? wyv.x : jj == 1 ? wyv.y : jj == 2 ? wyv.z : wyv.w;
+                const double w = (double)wxs * (double)wys;
+                fx += sF[cq.x].x * w;
+                fy += sF[cq.x].y * w;
             }
         }
         size_t i = (size_t)py * B.ps + px;
@@ -237,7 +260,6 @@ __global__ __launch_bounds__(256) void k_ib(const SimDev *__restrict__ sims, Bod
         B.fib[(size_t)B.ps * B.ps + i] = (float)fy;
     }
     if (bad) atomicOr(d_status, kStatusPatch);
-    (void)S;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -252,16 +274,20 @@ __device__ __forceinline__ int xcd_remap(int v, int n) {
     return x * q + min(x, r) + k;
 }
 
+__device__ __forceinline__ void inc_row(unsigned &r, unsigned ny) { r = (r + 1u == ny) ? 0u : r + 1u; }
+
 template <int T, typename HT>
 __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, const BodyDev *__restrict__ bodies,
                                              const WorkItem *__restrict__ items, int n_items, int cur,
                                              int *__restrict__ d_t) {
-    __shared__ double rP[5][2][T];   // polarization rows f-4 .. f
-    __shared__ float rS[4][3][T];    // stress rows f-4 .. f-1
-    __shared__ float rE[3][4][T];    // Ericksen stress rows f-3 .. f-1
-    __shared__ float rV[3][2][T];    // velocity rows f-4 .. f-2
-    __shared__ float rQs[3][3][T];   // predicted stress rows f-5 .. f-3
-    __shared__ double rQp[3][2][T];  // predicted polarization rows f-5 .. f-3
+    // row-exchange rings; values a thread needs only from its own column one row below live in
+    // registers (the "carried" row of the previous iteration)
+    __shared__ double rP[4][2][T];   // polarization rows f-3 .. f
+    __shared__ float rS[3][3][T];    // stress rows f-3 .. f-1
+    __shared__ float rE[2][2][T];    // Ericksen xx and yx, rows f-2 .. f-1
+    __shared__ float rV[2][2][T];    // velocity rows f-3 .. f-2
+    __shared__ float rQs[2][3][T];   // predicted stress rows f-4 .. f-3
+    __shared__ double rQp[2][2][T];  // predicted polarization rows f-4 .. f-3
     const int tid = threadIdx.x;
     const int nxt = cur ^ 1;
     if (blockIdx.x == 0 && tid == 0) d_t[0] = d_t[0] + 1;   // the body update after this step uses t+1
@@ -269,8 +295,8 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
     for (int vi = blockIdx.x; vi < n_items; vi += gridDim.x) {
         const WorkItem wi = items[xcd_remap(vi, n_items)];
         const SimDev &S = sims[wi.sim];
-        const int nx = S.nx, ny = S.ny;
-        const size_t N = (size_t)nx * ny;
+        const unsigned nx = (unsigned)S.nx, ny = (unsigned)S.ny;
+        const unsigned N = nx * ny;
         const HT *__restrict__ hin = reinterpret_cast<const HT *>(S.h[cur]);
         HT *__restrict__ hout = reinterpret_cast<HT *>(S.h[nxt]);
         const float *__restrict__ sgi = S.sig[cur];
@@ -278,137 +304,174 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
         const double *__restrict__ Pi = S.P[cur];
         double *__restrict__ Po = S.P[nxt];
         const int c = wi.x0 - kHalo + tid;
-        const int x = wrapi(c, nx), xm = wrapi(c - 1, nx), xp = wrapi(c + 1, nx);
+        const unsigned x = (unsigned)wrapi(c, (int)nx), xm = (unsigned)wrapi(c - 1, (int)nx),
+                       xp = (unsigned)wrapi(c + 1, (int)nx);
         const int wcol = wi.w;
         const bool colA = tid < wcol + 2 * kHalo;
         const bool colB = tid >= 1 && tid < wcol + 7;
         const bool colC = tid >= 2 && tid < wcol + 6;
         const bool colD = tid >= 3 && tid < wcol + 5;
         const bool colE = tid >= 4 && tid < wcol + 4;
+        const float is = S.inv_scale, sc = S.scale;
 
-        // corrector inputs frozen at time t: produced by stage D for row r in one iteration and
-        // consumed by stage E for the same row in the next one (stage D of that iteration has
-        // already moved on to row r+1, hence the separate "next" copies)
+        // wrapped row indices relative to the front row f of the current iteration
+        const int f0 = wi.y0 - 4;
+        unsigned rp1 = (unsigned)wrapi(f0 + 1, (int)ny), r0 = (unsigned)wrapi(f0, (int)ny);
+        unsigned rm1 = (unsigned)wrapi(f0 - 1, (int)ny), rm2 = (unsigned)wrapi(f0 - 2, (int)ny);
+        unsigned rm4 = (unsigned)wrapi(f0 - 4, (int)ny);
+
+        // rows the next iteration commits to LDS, loaded one iteration ahead
+        double qP0 = 0.0, qP1 = 0.0;
+        float qS0 = 0.f, qS1 = 0.f, qS2 = 0.f;
+        float qH[9];
+        if (colA) {
+            const unsigned iP = r0 * nx + x, iS = rm1 * nx + x;
+            qP0 = ld32(Pi, iP);
+            qP1 = ld32(Pi, N + iP);
+            qS0 = ld32(sgi, iS);
+            qS1 = ld32(sgi, N + iS);
+            qS2 = ld32(sgi, 2u * N + iS);
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) qH[q] = 0.f;
+
+        // row f-4 of this column, frozen at time t (stage D of the previous iteration): the
+        // corrector's inputs and the south neighbours of stage D
         float cvx = 0.f, cvy = 0.f, cs0 = 0.f, cs1 = 0.f, cs2 = 0.f;
         double cp0 = 0.0, cp1 = 0.0;
         Grad cg = {0.f, 0.f, 0.f, 0.f};
         Stiff ck = {0.f, 0.f, 0.f, 0.f};
+        // Ericksen xy, yy of this column at rows f-1, f-2, f-3
+        float exy1 = 0.f, eyy1 = 0.f, exy2 = 0.f, eyy2 = 0.f, exy3 = 0.f, eyy3 = 0.f;
+        // predicted stress and polarization of this column one row below the corrector row
+        float qs0 = 0.f, qs1 = 0.f, qs2 = 0.f;
+        double qp0 = 0.0, qp1 = 0.0;
 
         __syncthreads();
         const int niter = wi.l + 8;
         for (int j = 0; j < niter; ++j) {
-            const int f = wi.y0 - 4 + j;
-            // ring slot of row f - m is (j - m) mod (ring size); 60 keeps the operands positive
-            const int p0 = (j + 60) % 5, p1 = (j + 59) % 5, p2 = (j + 58) % 5, p3 = (j + 57) % 5, p4 = (j + 56) % 5;
-            const int s1 = (j + 59) & 3, s2 = (j + 58) & 3, s3 = (j + 57) & 3, s4 = (j + 56) & 3;
-            const int e1 = (j + 59) % 3, e2 = (j + 58) % 3, e3 = (j + 57) % 3;   // rows f-1, f-2, f-3
-            const int v2 = e2, v3 = e3, v4 = (j + 56) % 3;                       // rows f-2, f-3, f-4
-            const int q3 = e3, q4 = v4, q5 = (j + 55) % 3;                       // rows f-3, f-4, f-5
-
-            // ---- stage A: load P(f), sigma(f-1)
-            if (colA) {
-                const size_t iP = (size_t)wrapi(f, ny) * nx + x;
-                const size_t iS = (size_t)wrapi(f - 1, ny) * nx + x;
-                rP[p0][0][tid] = Pi[iP];
-                rP[p0][1][tid] = Pi[N + iP];
-                rS[s1][0][tid] = sgi[iS];
-                rS[s1][1][tid] = sgi[N + iS];
-                rS[s1][2][tid] = sgi[2 * N + iS];
-            }
-            // populations for stage C (row f-2), pulled: h_n(x, r) = h*_n(x - c_n, r - c_n)
-            float d[9];
+            const int a0 = j & 3, a1 = (j + 3) & 3, a2 = (j + 2) & 3, a3 = (j + 1) & 3;   // P rows f .. f-3
+            const int b1 = (j + 59) % 3, b2 = (j + 58) % 3, b3 = (j + 57) % 3;           // stress rows f-1 .. f-3
+            const int o1 = (j + 1) & 1, o0 = j & 1;   // rows f-1 / f-3 (odd lag) and f-2 / f-4 (even lag)
             const bool runC = j >= 4 && colC;
-            if (runC) {
-                const int r = f - 2;
-                const size_t yc = (size_t)wrapi(r, ny) * nx, ym = (size_t)wrapi(r - 1, ny) * nx,
-                             yp = (size_t)wrapi(r + 1, ny) * nx;
-                const float is = S.inv_scale;
-                d[0] = Pop<HT>::load(hin, 0 * N + yc + x, is);
-                d[1] = Pop<HT>::load(hin, 1 * N + yc + xm, is);
-                d[2] = Pop<HT>::load(hin, 2 * N + ym + x, is);
-                d[3] = Pop<HT>::load(hin, 3 * N + yc + xp, is);
-                d[4] = Pop<HT>::load(hin, 4 * N + yp + x, is);
-                d[5] = Pop<HT>::load(hin, 5 * N + ym + xm, is);
-                d[6] = Pop<HT>::load(hin, 6 * N + ym + xp, is);
-                d[7] = Pop<HT>::load(hin, 7 * N + yp + xp, is);
-                d[8] = Pop<HT>::load(hin, 8 * N + yp + xm, is);
+
+            // ---- stage A: commit P(f), sigma(f-1); take this iteration's populations
+            if (colA) {
+                rP[a0][0][tid] = qP0;
+                rP[a0][1][tid] = qP1;
+                rS[b1][0][tid] = qS0;
+                rS[b1][1][tid] = qS1;
+                rS[b1][2][tid] = qS2;
+            }
+            float d[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) d[q] = qH[q];
+            // prefetch for iteration j+1: P(f+1), sigma(f), and the populations pulled into row
+            // f-1: h_n(x, r) = h*_n(x - c_n, r - c_n) from rows f-2, f-1, f
+            if (j + 1 < niter) {
+                if (colA) {
+                    const unsigned iP = rp1 * nx + x, iS = r0 * nx + x;
+                    qP0 = ld32(Pi, iP);
+                    qP1 = ld32(Pi, N + iP);
+                    qS0 = ld32(sgi, iS);
+                    qS1 = ld32(sgi, N + iS);
+                    qS2 = ld32(sgi, 2u * N + iS);
+                }
+                if (j + 1 >= 4 && colC) {
+                    const unsigned yc = rm1 * nx, ym = rm2 * nx, yp = r0 * nx;
+                    qH[0] = Pop<HT>::ld(hin, yc + x, is);
+                    qH[1] = Pop<HT>::ld(hin, N + yc + xm, is);
+                    qH[2] = Pop<HT>::ld(hin, 2u * N + ym + x, is);
+                    qH[3] = Pop<HT>::ld(hin, 3u * N + yc + xp, is);
+                    qH[4] = Pop<HT>::ld(hin, 4u * N + yp + x, is);
+                    qH[5] = Pop<HT>::ld(hin, 5u * N + ym + xm, is);
+                    qH[6] = Pop<HT>::ld(hin, 6u * N + ym + xp, is);
+                    qH[7] = Pop<HT>::ld(hin, 7u * N + yp + xp, is);
+                    qH[8] = Pop<HT>::ld(hin, 8u * N + yp + xm, is);
+                }
             }
             __syncthreads();
 
             // ---- stage B: Ericksen stress at row f-1
+            exy3 = exy2;
+            eyy3 = eyy2;
+            exy2 = exy1;
+            eyy2 = eyy1;
             if (j >= 2 && colB) {
-                double Pc[2] = {rP[p1][0][tid], rP[p1][1][tid]};
-                double Pe[2] = {rP[p1][0][tid + 1], rP[p1][1][tid + 1]};
-                double Pw[2] = {rP[p1][0][tid - 1], rP[p1][1][tid - 1]};
-                double Pn[2] = {rP[p0][0][tid], rP[p0][1][tid]};
-                double Ps[2] = {rP[p2][0][tid], rP[p2][1][tid]};
+                double Pc[2] = {rP[a1][0][tid], rP[a1][1][tid]};
+                double Pe[2] = {rP[a1][0][tid + 1], rP[a1][1][tid + 1]};
+                double Pw[2] = {rP[a1][0][tid - 1], rP[a1][1][tid - 1]};
+                double Pn[2] = {rP[a0][0][tid], rP[a0][1][tid]};
+                double Ps[2] = {rP[a2][0][tid], rP[a2][1][tid]};
                 float E[4];
                 ericksen(S, Pc, Pe, Pw, Pn, Ps, E);
-                rE[e1][0][tid] = E[0];
-                rE[e1][1][tid] = E[1];
-                rE[e1][2][tid] = E[2];
-                rE[e1][3][tid] = E[3];
+                rE[o1][0][tid] = E[0];
+                rE[o1][1][tid] = E[2];
+                exy1 = E[1];
+                eyy1 = E[3];
             }
             __syncthreads();
 
             // ---- stage C: force, moments, collision at row f-2
             if (runC) {
-                const int r = f - 2;
-                const int yw = wrapi(r, ny);
-                float Fx = 0.5f * (rS[s2][0][tid + 1] - rS[s2][0][tid - 1]) + 0.5f * (rS[s1][2][tid] - rS[s3][2][tid]);
-                float Fy = 0.5f * (rS[s2][2][tid + 1] - rS[s2][2][tid - 1]) + 0.5f * (rS[s1][1][tid] - rS[s3][1][tid]);
+                float Fx = 0.5f * (rS[b2][0][tid + 1] - rS[b2][0][tid - 1]) + 0.5f * (rS[b1][2][tid] - rS[b3][2][tid]);
+                float Fy = 0.5f * (rS[b2][2][tid + 1] - rS[b2][2][tid - 1]) + 0.5f * (rS[b1][1][tid] - rS[b3][1][tid]);
                 if (S.ericksen) {
-                    Fx += 0.5f * (rE[e2][0][tid + 1] - rE[e2][0][tid - 1]) + 0.5f * (rE[e1][1][tid] - rE[e3][1][tid]);
-                    Fy += 0.5f * (rE[e2][2][tid + 1] - rE[e2][2][tid - 1]) + 0.5f * (rE[e1][3][tid] - rE[e3][3][tid]);
+                    Fx += 0.5f * (rE[o0][0][tid + 1] - rE[o0][0][tid - 1]) + 0.5f * (exy1 - exy3);
+                    Fy += 0.5f * (rE[o0][1][tid + 1] - rE[o0][1][tid - 1]) + 0.5f * (eyy1 - eyy3);
                 }
-                if (S.nb) ib_force(S, bodies, cur, x, yw, Fx, Fy);
+                if (S.nb) ib_force(S, bodies, cur, (int)x, (int)rm2, Fx, Fy);
                 float drho, ux, uy;
                 collide(d, Fx, Fy, S.omega, S.guo, drho, ux, uy);
-                rV[v2][0][tid] = ux;
-                rV[v2][1][tid] = uy;
+                rV[o0][0][tid] = ux;
+                rV[o0][1][tid] = uy;
+                const int r = wi.y0 + j - 6;   // = f - 2
                 if (colE && r >= wi.y0 && r < wi.y0 + wi.l) {
-                    const size_t o = (size_t)yw * nx + x;
-                    const float sc = S.scale;
+                    const unsigned o = rm2 * nx + x;
 #pragma unroll
-                    for (int q = 0; q < 9; ++q) Pop<HT>::store(hout, q * N + o, d[q], sc);
-                    if (S.nb) ib_store_v(S, bodies, cur, x, yw, ux, uy);
+                    for (int q = 0; q < 9; ++q) Pop<HT>::st(hout, (unsigned)q * N + o, d[q], sc);
+                    if (S.nb) ib_store_v(S, bodies, cur, (int)x, (int)rm2, ux, uy);
                 }
             }
             __syncthreads();
 
-            // ---- stage D: predictor at row f-3
+            // ---- stage D: predictor at row f-3 (from j = 5 only the carried centre values)
             float nvx = 0.f, nvy = 0.f, ns0 = 0.f, ns1 = 0.f, ns2 = 0.f;
             double np0 = 0.0, np1 = 0.0;
             Grad ng = {0.f, 0.f, 0.f, 0.f};
             Stiff nk = {0.f, 0.f, 0.f, 0.f};
-            if (j >= 6 && colD) {
-                ng = grad_v(rV[v3][0][tid + 1], rV[v3][0][tid - 1], rV[v2][0][tid], rV[v4][0][tid],
-                            rV[v3][1][tid + 1], rV[v3][1][tid - 1], rV[v2][1][tid], rV[v4][1][tid]);
-                nvx = rV[v3][0][tid];
-                nvy = rV[v3][1][tid];
-                double Pc[2] = {rP[p3][0][tid], rP[p3][1][tid]};
-                double Pe[2] = {rP[p3][0][tid + 1], rP[p3][1][tid + 1]};
-                double Pw[2] = {rP[p3][0][tid - 1], rP[p3][1][tid - 1]};
-                double Pn[2] = {rP[p2][0][tid], rP[p2][1][tid]};
-                double Ps[2] = {rP[p4][0][tid], rP[p4][1][tid]};
-                nk = stiffness(S, (float)Pc[0], (float)Pc[1]);
-                float X[3], Xe[3], Xw[3], Xn[3], Xs[3], Rs[3];
+            if (j >= 5 && colD) {
+                nvx = rV[o1][0][tid];
+                nvy = rV[o1][1][tid];
+                double Pc[2] = {rP[a3][0][tid], rP[a3][1][tid]};
+                float X[3];
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    X[q] = rS[s3][q][tid];
-                    Xe[q] = rS[s3][q][tid + 1];
-                    Xw[q] = rS[s3][q][tid - 1];
-                    Xn[q] = rS[s2][q][tid];
-                    Xs[q] = rS[s4][q][tid];
+                for (int q = 0; q < 3; ++q) X[q] = rS[b3][q][tid];
+                if (j >= 6) {
+                    ng = grad_v(rV[o1][0][tid + 1], rV[o1][0][tid - 1], rV[o0][0][tid], cvx,
+                                rV[o1][1][tid + 1], rV[o1][1][tid - 1], rV[o0][1][tid], cvy);
+                    double Pe[2] = {rP[a3][0][tid + 1], rP[a3][1][tid + 1]};
+                    double Pw[2] = {rP[a3][0][tid - 1], rP[a3][1][tid - 1]};
+                    double Pn[2] = {rP[a2][0][tid], rP[a2][1][tid]};
+                    double Ps[2] = {cp0, cp1};
+                    nk = stiffness(S, (float)Pc[0], (float)Pc[1]);
+                    float Xe[3], Xw[3], Xn[3], Rs[3];
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        Xe[q] = rS[b3][q][tid + 1];
+                        Xw[q] = rS[b3][q][tid - 1];
+                        Xn[q] = rS[b2][q][tid];
+                    }
+                    const float Xs[3] = {cs0, cs1, cs2};
+                    rhs_sigma(S, nk, ng, nvx, nvy, X, Xe, Xw, Xn, Xs, Rs);
+                    double Rp[2];
+                    rhs_P(S, ng, nvx, nvy, Pc, Pe, Pw, Pn, Ps, Rp);
+                    rQs[o1][0][tid] = X[0] + Rs[0];
+                    rQs[o1][1][tid] = X[1] + Rs[1];
+                    rQs[o1][2][tid] = X[2] + Rs[2];
+                    rQp[o1][0][tid] = Pc[0] + Rp[0];
+                    rQp[o1][1][tid] = Pc[1] + Rp[1];
                 }
-                rhs_sigma(S, nk, ng, nvx, nvy, X, Xe, Xw, Xn, Xs, Rs);
-                double Rp[2];
-                rhs_P(S, ng, nvx, nvy, Pc, Pe, Pw, Pn, Ps, Rp);
-                rQs[q3][0][tid] = X[0] + Rs[0];
-                rQs[q3][1][tid] = X[1] + Rs[1];
-                rQs[q3][2][tid] = X[2] + Rs[2];
-                rQp[q3][0][tid] = Pc[0] + Rp[0];
-                rQp[q3][1][tid] = Pc[1] + Rp[1];
                 ns0 = X[0];
                 ns1 = X[1];
                 ns2 = X[2];
@@ -417,37 +480,46 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             }
             __syncthreads();
 
-            // ---- stage E: corrector at row f-4, with the inputs stage D froze one iteration ago
-            if (j >= 8 && colE) {
-                const int r = f - 4;
-                float X[3], Xe[3], Xw[3], Xn[3], Xs[3], Rs[3];
+            // ---- stage E: corrector at row f-4 with the inputs stage D froze one iteration ago;
+            // from j = 7 it records the predicted centre values as next iteration's south row
+            if (j >= 7 && colE) {
+                float X[3], Xe[3], Xw[3], Xn[3], Rs[3];
+                double Y[2], Ye[2], Yw[2], Yn[2], Rp[2];
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    X[q] = rQs[q4][q][tid];
-                    Xe[q] = rQs[q4][q][tid + 1];
-                    Xw[q] = rQs[q4][q][tid - 1];
-                    Xn[q] = rQs[q3][q][tid];
-                    Xs[q] = rQs[q5][q][tid];
-                }
-                rhs_sigma(S, ck, cg, cvx, cvy, X, Xe, Xw, Xn, Xs, Rs);
-                double Y[2], Ye[2], Yw[2], Yn[2], Ys[2], Rp[2];
+                for (int q = 0; q < 3; ++q) X[q] = rQs[o0][q][tid];
+                Y[0] = rQp[o0][0][tid];
+                Y[1] = rQp[o0][1][tid];
+                if (j >= 8) {
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    Y[q] = rQp[q4][q][tid];
-                    Ye[q] = rQp[q4][q][tid + 1];
-                    Yw[q] = rQp[q4][q][tid - 1];
-                    Yn[q] = rQp[q3][q][tid];
-                    Ys[q] = rQp[q5][q][tid];
+                    for (int q = 0; q < 3; ++q) {
+                        Xe[q] = rQs[o0][q][tid + 1];
+                        Xw[q] = rQs[o0][q][tid - 1];
+                        Xn[q] = rQs[o1][q][tid];
+                    }
+                    const float Xs[3] = {qs0, qs1, qs2};
+                    rhs_sigma(S, ck, cg, cvx, cvy, X, Xe, Xw, Xn, Xs, Rs);
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        Ye[q] = rQp[o0][q][tid + 1];
+                        Yw[q] = rQp[o0][q][tid - 1];
+                        Yn[q] = rQp[o1][q][tid];
+                    }
+                    const double Ys[2] = {qp0, qp1};
+                    rhs_P(S, cg, cvx, cvy, Y, Ye, Yw, Yn, Ys, Rp);
+                    const unsigned o = rm4 * nx + x;
+                    st32(sgo, o, 0.5f * ((cs0 + X[0]) + Rs[0]));
+                    st32(sgo, N + o, 0.5f * ((cs1 + X[1]) + Rs[1]));
+                    st32(sgo, 2u * N + o, 0.5f * ((cs2 + X[2]) + Rs[2]));
+                    st32(Po, o, 0.5 * ((cp0 + Y[0]) + Rp[0]));
+                    st32(Po, N + o, 0.5 * ((cp1 + Y[1]) + Rp[1]));
                 }
-                rhs_P(S, cg, cvx, cvy, Y, Ye, Yw, Yn, Ys, Rp);
-                const size_t o = (size_t)wrapi(r, ny) * nx + x;
-                sgo[o] = 0.5f * ((cs0 + X[0]) + Rs[0]);
-                sgo[N + o] = 0.5f * ((cs1 + X[1]) + Rs[1]);
-                sgo[2 * N + o] = 0.5f * ((cs2 + X[2]) + Rs[2]);
-                Po[o] = 0.5 * ((cp0 + Y[0]) + Rp[0]);
-                Po[N + o] = 0.5 * ((cp1 + Y[1]) + Rp[1]);
+                qs0 = X[0];
+                qs1 = X[1];
+                qs2 = X[2];
+                qp0 = Y[0];
+                qp1 = Y[1];
             }
-            // commit the frozen inputs of row f-3 for next iteration's corrector
+            // row f-3 becomes next iteration's row f-4
             cvx = nvx;
             cvy = nvy;
             cg = ng;
@@ -457,6 +529,11 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             cs2 = ns2;
             cp0 = np0;
             cp1 = np1;
+            inc_row(rp1, ny);
+            inc_row(r0, ny);
+            inc_row(rm1, ny);
+            inc_row(rm2, ny);
+            inc_row(rm4, ny);
         }
     }
 }
@@ -827,6 +904,18 @@ hipError_t launch_fused(int T, bool fp16, int grid, hipStream_t st, const SimDev
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+int fused_blocks_per_cu(int T, bool fp16) {
+    int n = 0;
+    hipError_t e;
+    if (T == 128)
+        e = fp16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fused<128, __half>, 128, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fused<128, float>, 128, 0);
+    else
+        e = fp16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fused<256, __half>, 256, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fused<256, float>, 256, 0);
+    return e == hipSuccess && n > 0 ? n : 1;
 }
 
 hipError_t launch_multipass(bool fp16, int nblocks, hipStream_t st, const SimDev *sims, const BodyDev *bodies,

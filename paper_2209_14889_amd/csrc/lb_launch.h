@@ -10,6 +10,8 @@ hipError_t launch_ib(bool advance, int nblocks, hipStream_t st, const SimDev *si
                      int cur, const int *d_t, int *d_status);
 hipError_t launch_fused(int T, bool fp16, int grid, hipStream_t st, const SimDev *sims, const BodyDev *bodies,
                         const WorkItem *items, int n_items, int cur, int *d_t);
+// resident fused work-groups per compute unit for work-group size T
+int fused_blocks_per_cu(int T, bool fp16);
 hipError_t launch_multipass(bool fp16, int nblocks, hipStream_t st, const SimDev *sims, const BodyDev *bodies,
                             const SiteBlock *blk, int cur, int *d_t);
 hipError_t launch_readout(bool fp16, int nblocks, int block0, hipStream_t st, const SimDev *sims,
