@@ -134,7 +134,8 @@ def main():
     # roofline of the dominant kernel: HIP events around every field-kernel launch on the
     # library's stream (plain launches, same kernel and launch configuration)
     topt = lb.make_options(precision=precision, kernel=args.kernel, timing=1, seg_rows=shape["seg_rows"],
-                           fused_threads=shape["threads"])
+                           fused_threads=shape["threads"],
+                           grid=shape["grid"] if shape["grid"] < shape["n_items"] else 0)
     tsim = lb.Sim(w, topt)
     tsim.step(20)
     tsim.timing(reset=True)
@@ -169,7 +170,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "sites": sites,
                    "kernel": "fused" if args.kernel == 0 else "multipass", "graph_chunk": args.graph_chunk,
-                   "threads": shape["threads"], "seg_rows": shape["seg_rows"], "work_items": shape["n_items"]},
+                   "threads": shape["threads"], "seg_rows": shape["seg_rows"], "work_items": shape["n_items"],
+                   "grid": shape["grid"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_fused", "bytes_per_site": bps, "launch_us": round(avg_ms * 1e3, 3)},

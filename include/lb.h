@@ -84,9 +84,11 @@ typedef struct {
     int32_t seg_rows;           /* rows per fused work item; 0 = tuned default */
     int32_t fused_threads;      /* fused work-group size: 128 or 256 (strip of 120 or 248
                                    columns); 0 = chosen from the lattice width */
-    int32_t autotune;           /* 1: time candidate (work-group size, rows per item) pairs on the
-                                   live state in lb_create and keep the fastest; 0: cost model */
-    int32_t reserved[3];
+    int32_t autotune;           /* 1: time candidate (work-group size, rows per item, grid) shapes on
+                                   the live state in lb_create and keep the fastest; 0: cost model */
+    int32_t grid;               /* fused work-groups launched: 0 = one per work item; > 0 = a
+                                   persistent grid of that many looping over the items */
+    int32_t reserved[2];
 } lb_options;
 
 /* Bytes of device memory lb_create needs for these simulations (arena for all state, tables,
@@ -147,8 +149,11 @@ int lb_timing(lb_handle *h, double *field_ms, int64_t *field_launches, double *i
               int64_t *ib_launches, int32_t reset);
 
 /* Fused-kernel launch shape in use: work-group size, rows per work item, number of work items,
- * and (after autotuning) the measured milliseconds per launch of the chosen shape (else 0). */
-int lb_launch_shape(lb_handle *h, int32_t *threads, int32_t *seg_rows, int32_t *n_items, double *tuned_ms);
+ * work-groups launched (fewer than the items: a persistent grid looping over them), and (after
+ * autotuning) the measured milliseconds per launch of the chosen shape (else 0).  Any output
+ * pointer may be NULL. */
+int lb_launch_shape(lb_handle *h, int32_t *threads, int32_t *seg_rows, int32_t *n_items, int32_t *grid,
+                    double *tuned_ms);
 
 /* Release the handle's host resources (and its stream if the library created it). */
 int lb_destroy(lb_handle *h);

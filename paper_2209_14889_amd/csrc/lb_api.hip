@@ -173,7 +173,7 @@ struct Plan {
 
 struct Opt {
     int precision = 0, shift = kDefaultShift, watchdog = 0, chunk = 0, kernel = 0, timing = 0, seg = 0, threads = 0;
-    int autotune = 0;
+    int autotune = 0, grid = 0;
 };
 
 Opt read_opt(const lb_options *o) {
@@ -188,6 +188,7 @@ Opt read_opt(const lb_options *o) {
     r.seg = o->seg_rows;
     r.threads = o->fused_threads;
     r.autotune = o->autotune;
+    r.grid = o->grid;
     return r;
 }
 
@@ -214,6 +215,7 @@ int validate(const lb_sim_params *sims, int n_sims, const Opt &o) {
     if (o.chunk < 0 || (o.chunk & 1)) return fail(LB_EINVAL, "graph_chunk must be even and >= 0");
     if (o.threads != 0 && o.threads != 128 && o.threads != 256) return fail(LB_EINVAL, "fused_threads must be 0, 128 or 256");
     if (o.seg < 0) return fail(LB_EINVAL, "seg_rows must be >= 0");
+    if (o.grid < 0) return fail(LB_EINVAL, "grid must be >= 0");
     for (int s = 0; s < n_sims; ++s) {
         const lb_sim_params &p = sims[s];
         if (p.nx < 8 || p.ny < 8 || p.nx > 16384 || p.ny > 16384) return fail(LB_EINVAL, "sim %d: lattice size out of range", s);
@@ -495,7 +497,9 @@ int launch_step(lb_handle *h, bool timed) {
     return LB_OK;
 }
 
-int upload_items(lb_handle *h, int T, int seg) {
+// grid: 0 = one work-group per item; > 0 = persistent grid of that many work-groups (a multiple
+// of 8, so each XCD keeps a contiguous run of items) looping over the item table
+int upload_items(lb_handle *h, int T, int seg, int grid = 0) {
     std::vector<WorkItem> items = build_items(h->plan.sims, T, seg);
     if (items.size() > h->plan.items.size()) return fail(LB_EINVAL, "internal: work-item table overflow");
     HIPCHK(hipMemcpyAsync(h->d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, h->stream));
@@ -503,7 +507,7 @@ int upload_items(lb_handle *h, int T, int seg) {
     h->fused_T = T;
     h->fused_seg = seg;
     h->n_items = (int)items.size();
-    h->fused_grid = h->n_items;
+    h->fused_grid = (grid > 0 && grid < h->n_items) ? grid : h->n_items;
     return LB_OK;
 }
 
@@ -527,15 +531,23 @@ int choose_fused_config(lb_handle *h) {
     if (!h->opt.autotune) {
         int T = model_T();
         int seg = h->opt.seg ? h->opt.seg : model_seg(h->plan.sims, T, cus * fused_blocks_per_cu(T, fp16));
-        return upload_items(h, T, seg);
+        return upload_items(h, T, seg, h->opt.grid);
     }
-    std::vector<std::pair<int, int>> cand;
+    struct Cand {
+        int T, seg, grid;
+        bool operator==(const Cand &o) const { return T == o.T && seg == o.seg && grid == o.grid; }
+    };
+    std::vector<Cand> cand;
     for (int T : {128, 256}) {
         if (h->opt.threads && T != h->opt.threads) continue;
         int slots = cus * fused_blocks_per_cu(T, fp16);
         int m = model_seg(h->plan.sims, T, slots);
-        for (int seg : {m, std::max(4, m / 2), m * 2, m + 4, std::max(4, m - 4)})
-            if (std::find(cand.begin(), cand.end(), std::make_pair(T, seg)) == cand.end()) cand.emplace_back(T, seg);
+        for (int seg : {m, std::max(4, m / 2), m * 2, m + 4, std::max(4, m - 4), 64}) {
+            for (int grid : {0, (slots / 8) * 8}) {
+                Cand c{T, seg, grid};
+                if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+            }
+        }
     }
     int t_saved = 0;
     HIPCHK(hipMemcpy(&t_saved, h->d_t, sizeof(int), hipMemcpyDeviceToHost));
@@ -545,23 +557,23 @@ int choose_fused_config(lb_handle *h) {
     // warm the clocks with the first candidate, then time every candidate in two passes and
     // keep each one's best pass (clock ramps and neighbours on the device add noise)
     {
-        int rc = upload_items(h, cand.front().first, cand.front().second);
+        int rc = upload_items(h, cand.front().T, cand.front().seg, cand.front().grid);
         if (rc) return rc;
         for (int r = 0; r < 30; ++r)
-            HIPCHK(launch_fused(cand.front().first, fp16, h->fused_grid, h->stream, h->d_sims, h->d_bodies,
+            HIPCHK(launch_fused(cand.front().T, fp16, h->fused_grid, h->stream, h->d_sims, h->d_bodies,
                                 h->d_items, h->n_items, h->cur, h->d_t));
     }
     std::vector<float> tbest(cand.size(), 1e30f);
     for (int pass = 0; pass < 2; ++pass) {
         for (size_t ci = 0; ci < cand.size(); ++ci) {
-            const auto c = cand[ci];
-            int rc = upload_items(h, c.first, c.second);
+            const Cand c = cand[ci];
+            int rc = upload_items(h, c.T, c.seg, c.grid);
             if (rc) return rc;
-            HIPCHK(launch_fused(c.first, fp16, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
+            HIPCHK(launch_fused(c.T, fp16, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
                                 h->n_items, h->cur, h->d_t));
             HIPCHK(hipEventRecord(e0, h->stream));
             for (int r = 0; r < 8; ++r)
-                HIPCHK(launch_fused(c.first, fp16, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
+                HIPCHK(launch_fused(c.T, fp16, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
                                     h->n_items, h->cur, h->d_t));
             HIPCHK(hipEventRecord(e1, h->stream));
             HIPCHK(hipEventSynchronize(e1));
@@ -573,13 +585,13 @@ int choose_fused_config(lb_handle *h) {
     size_t bi = 0;
     for (size_t ci = 1; ci < cand.size(); ++ci)
         if (tbest[ci] < tbest[bi]) bi = ci;
-    const std::pair<int, int> pick = cand[bi];
+    const Cand pick = cand[bi];
     const float best = tbest[bi];
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIPCHK(hipMemcpy(h->d_t, &t_saved, sizeof(int), hipMemcpyHostToDevice));
     h->tuned_ms = best;
-    return upload_items(h, pick.first, pick.second);
+    return upload_items(h, pick.T, pick.seg, pick.grid);
 }
 
 int run_watchdog(lb_handle *h) {
@@ -798,6 +810,8 @@ static int create_impl(const lb_sim_params *sims, int n_sims, const lb_options *
                     R[2 * a + 1] = bd.cy + bd.radius * std::sin(ang);
                 }
             }
+            const int zero_origin[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            HIPCHK(hipMemcpyAsync(B.origin, zero_origin, sizeof zero_origin, hipMemcpyHostToDevice, h->stream));
             HIPCHK(hipMemcpyAsync(B.R[0], R.data(), R.size() * 8, hipMemcpyHostToDevice, h->stream));
             HIPCHK(hipMemcpyAsync(B.R[1], R.data(), R.size() * 8, hipMemcpyHostToDevice, h->stream));
             HIPCHK(hipStreamSynchronize(h->stream));
@@ -815,8 +829,6 @@ static int create_impl(const lb_sim_params *sims, int n_sims, const lb_options *
     HIPCHK(hipMemcpyAsync(h->d_t, zero, sizeof(int), hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipMemcpyAsync(h->d_status, zero, sizeof(int), hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
-    rc = choose_fused_config(h.get());
-    if (rc) return rc;
 
     // initial body forces spread onto their patches
     if (!pl.ib_blk.empty())
@@ -830,6 +842,11 @@ static int create_impl(const lb_sim_params *sims, int n_sims, const lb_options *
         HIPCHK(hipStreamSynchronize(h->stream));
         h->mass0.push_back(m[0]);
     }
+    // launch shape of the fused kernel; the autotuner runs the kernel, so only now that every
+    // body's patch origin and spread force exist
+    HIPCHK(hipStreamSynchronize(h->stream));
+    rc = choose_fused_config(h.get());
+    if (rc) return rc;
     HIPCHK(hipHostMalloc((void **)&h->h_status, sizeof(int), hipHostMallocDefault));
     *h->h_status = 0;
     HIPCHK(hipEventCreateWithFlags(&h->ev_wd, hipEventDisableTiming));
@@ -1008,11 +1025,13 @@ int lb_timing(lb_handle *h, double *field_ms, int64_t *field_n, double *ib_ms, i
     return LB_OK;
 }
 
-int lb_launch_shape(lb_handle *h, int32_t *threads, int32_t *seg_rows, int32_t *n_items, double *tuned_ms) {
+int lb_launch_shape(lb_handle *h, int32_t *threads, int32_t *seg_rows, int32_t *n_items, int32_t *grid,
+                    double *tuned_ms) {
     if (!h) return fail(LB_EINVAL, "handle is NULL");
     if (threads) *threads = h->fused_T;
     if (seg_rows) *seg_rows = h->fused_seg;
     if (n_items) *n_items = h->n_items;
+    if (grid) *grid = h->fused_grid;
     if (tuned_ms) *tuned_ms = h->tuned_ms;
     return LB_OK;
 }

@@ -230,7 +230,7 @@ __device__ __forceinline__ void ib_force(const SimDev &S, const BodyDev *bodies,
         const BodyDev &B = bodies[S.b0 + b];
         int px = wrap_near(x - gptr(B.origin)[4 * parity + 2], S.nx);
         int py = wrap_near(y - gptr(B.origin)[4 * parity + 3], S.ny);
-        if (px < B.ps && py < B.ps) {
+        if ((unsigned)px < (unsigned)B.ps && (unsigned)py < (unsigned)B.ps) {
             unsigned i = (unsigned)(py * B.ps + px);
             Fx += gptr(B.fib)[i];
             Fy += gptr(B.fib)[(unsigned)(B.ps * B.ps) + i];
@@ -245,7 +245,7 @@ __device__ __forceinline__ void ib_store_v(const SimDev &S, const BodyDev *bodie
         const BodyDev &B = bodies[S.b0 + b];
         int px = wrap_near(x - gptr(B.origin)[4 * parity + 2], S.nx);
         int py = wrap_near(y - gptr(B.origin)[4 * parity + 3], S.ny);
-        if (px < B.ps && py < B.ps) {
+        if ((unsigned)px < (unsigned)B.ps && (unsigned)py < (unsigned)B.ps) {
             unsigned i = (unsigned)(py * B.ps + px);
             gptr(B.vib)[i] = ux;
             gptr(B.vib)[(unsigned)(B.ps * B.ps) + i] = uy;

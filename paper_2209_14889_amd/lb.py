@@ -52,7 +52,8 @@ class Options(ctypes.Structure):
         ("precision", ctypes.c_int32), ("fp16_shift", ctypes.c_int32),
         ("watchdog_every", ctypes.c_int32), ("graph_chunk", ctypes.c_int32),
         ("kernel", ctypes.c_int32), ("timing", ctypes.c_int32), ("seg_rows", ctypes.c_int32),
-        ("fused_threads", ctypes.c_int32), ("autotune", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
+        ("fused_threads", ctypes.c_int32), ("autotune", ctypes.c_int32), ("grid", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -86,7 +87,7 @@ def lib():
                                 ctypes.c_int32]
         L.lb_destroy.argtypes = [vp]
         L.lb_launch_shape.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                                      ctypes.POINTER(ctypes.c_int32), _dp]
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _dp]
         L.lb_last_error.restype = ctypes.c_char_p
         for name in ("lb_query_arena_bytes", "lb_create", "lb_step", "lb_read_fields", "lb_body_force",
                      "lb_conservation", "lb_sync", "lb_time", "lb_timing", "lb_destroy", "lb_launch_shape"):
@@ -102,11 +103,11 @@ def check(rc: int) -> None:
 
 def make_options(precision: int = 0, fp16_shift: int = 0, watchdog_every: int = 0, graph_chunk: int = 0,
                  kernel: int = 0, timing: int = 0, seg_rows: int = 0, fused_threads: int = 0,
-                 autotune: int = 0) -> Options:
+                 autotune: int = 0, grid: int = 0) -> Options:
     o = Options()
     o.precision, o.fp16_shift, o.watchdog_every, o.graph_chunk = precision, fp16_shift, watchdog_every, graph_chunk
     o.kernel, o.timing, o.seg_rows, o.fused_threads = kernel, timing, seg_rows, fused_threads
-    o.autotune = autotune
+    o.autotune, o.grid = autotune, grid
     return o
 
 
@@ -247,10 +248,11 @@ class Sim:
         return dict(field_ms=fm.value, field_launches=fn.value, ib_ms=im.value, ib_launches=inn.value)
 
     def launch_shape(self) -> dict:
-        t, sg, ni = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        t, sg, ni, gr = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
         ms = ctypes.c_double(0)
-        check(lib().lb_launch_shape(self.h, ctypes.byref(t), ctypes.byref(sg), ctypes.byref(ni), ctypes.byref(ms)))
-        return dict(threads=t.value, seg_rows=sg.value, n_items=ni.value, tuned_ms=ms.value)
+        check(lib().lb_launch_shape(self.h, ctypes.byref(t), ctypes.byref(sg), ctypes.byref(ni), ctypes.byref(gr),
+                                    ctypes.byref(ms)))
+        return dict(threads=t.value, seg_rows=sg.value, n_items=ni.value, grid=gr.value, tuned_ms=ms.value)
 
     def close(self) -> None:
         if getattr(self, "h", None):
