@@ -61,6 +61,27 @@ def workload(name: str, steps: int):
     raise SystemExit(f"unknown workload {name}")
 
 
+KERNEL_SOURCES = ["paper_2209_14889_amd/csrc/lb_kernels.hip", "paper_2209_14889_amd/csrc/lb_device.h",
+                  "paper_2209_14889_amd/csrc/lb_common.h"]
+
+
+def counted_traffic(workload_name: str, shape: dict):
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary (copy-kernel calibrated), or None when that summary is for another workload or launch
+    shape, or the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_fused_{workload_name}_2048x2048_fp16_hbm_counters.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read() for p in KERNEL_SOURCES)).hexdigest()
+    if d.get("sources_sha256") != h or d.get("workload") != workload_name:
+        return None
+    if d["launch"]["threads"] != shape["threads"] or d["launch"]["seg_rows"] != shape["seg_rows"]:
+        return None
+    return round(d["traffic_bytes"] / 1e9, 4)
+
+
 def cpu_baseline(w, name: str, budget_s: float = 15.0):
     """FP64 oracle on the host: the full coupled step on the workload's first simulation for as
     many steps as fit in about budget_s seconds (at least 2)."""
@@ -99,7 +120,19 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 256 MiB device buffer 5 times (reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = 64 * 1024 * 1024
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copied {n * 4} bytes 5 times")
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no multi-GPU "
               "path; independent simulations shard across GPUs with no exchange and one large lattice would "
@@ -173,7 +206,9 @@ def main():
                    "threads": shape["threads"], "seg_rows": shape["seg_rows"], "work_items": shape["n_items"],
                    "grid": shape["grid"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": counted_traffic(args.workload, shape),
+                     "traffic_unit": "GB per launch", "algorithmic_gb_per_launch": round(bps * sites / 1e9, 4),
                      "kernel": "k_fused", "bytes_per_site": bps, "launch_us": round(avg_ms * 1e3, 3)},
         "cpu_baseline": cpu,
     }

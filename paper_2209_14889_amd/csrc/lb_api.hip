@@ -146,7 +146,7 @@ struct Arena {
 
 struct BodyPlan {
     int sim, n, ps, nside;
-    size_t oR0, oR1, oF, oOrigin, oFib, oVib;
+    size_t oR0, oR1, oF, oOrigin, oFib, oVib, oNw, oNix;
 };
 
 struct SimPlan {
@@ -300,6 +300,8 @@ Plan make_plan(const lb_sim_params *sims, int n_sims, const Opt &o) {
             bp.oOrigin = a.take(8 * sizeof(int));
             bp.oFib = a.take(2 * (size_t)bp.ps * bp.ps * 4);
             bp.oVib = a.take(2 * (size_t)bp.ps * bp.ps * 4);
+            bp.oNw = a.take(32 * (size_t)bp.n);
+            bp.oNix = a.take(8 * (size_t)bp.n);
             for (int q = 0; q < bp.nside * bp.nside; ++q) pl.ib_blk.push_back(make_int2((int)pl.bodies.size(), q));
             pl.bodies.push_back(bp);
         }
@@ -481,8 +483,8 @@ int launch_step(lb_handle *h, bool timed) {
             if (!c || !d) return fail(LB_EDEVICE, "hipEventCreate failed");
             HIPCHK(hipEventRecord(c, h->stream));
         }
-        HIPCHK(launch_ib(true, (int)h->plan.ib_blk.size(), h->stream, h->d_sims, h->d_bodies, h->d_ib, h->cur, h->d_t,
-                         h->d_status));
+        HIPCHK(launch_ib(true, (int)h->plan.bodies.size(), (int)h->plan.ib_blk.size(), h->stream, h->d_sims,
+                         h->d_bodies, h->d_ib, h->cur, h->d_t, h->d_status));
         if (timed) {
             HIPCHK(hipEventRecord(d, h->stream));
             h->pending_ib.emplace_back(c, d);
@@ -799,6 +801,8 @@ static int create_impl(const lb_sim_params *sims, int n_sims, const lb_options *
             B.origin = A.ptr<int>(bp.oOrigin);
             B.fib = A.ptr<float>(bp.oFib);
             B.vib = A.ptr<float>(bp.oVib);
+            B.nw = A.ptr<float>(bp.oNw);
+            B.nix = A.ptr<int>(bp.oNix);
             std::vector<double> R(2 * (size_t)bd.n_nodes);
             for (int a = 0; a < bd.n_nodes; ++a) {
                 if (bd.nodes) {
@@ -832,7 +836,8 @@ static int create_impl(const lb_sim_params *sims, int n_sims, const lb_options *
 
     // initial body forces spread onto their patches
     if (!pl.ib_blk.empty())
-        HIPCHK(launch_ib(false, (int)pl.ib_blk.size(), h->stream, h->d_sims, h->d_bodies, h->d_ib, 0, h->d_t, h->d_status));
+        HIPCHK(launch_ib(false, (int)pl.bodies.size(), (int)pl.ib_blk.size(), h->stream, h->d_sims, h->d_bodies,
+                         h->d_ib, 0, h->d_t, h->d_status));
     // reference mass for the watchdog
     for (int s = 0; s < n_sims; ++s) {
         int nb = std::min(pl.max_partial, pl.sims[s].nblk);

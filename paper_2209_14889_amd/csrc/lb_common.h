@@ -8,6 +8,7 @@ namespace lbk {
 constexpr int kMaxNodes = 1024;     // nodes per body
 constexpr int kMaxBodies = 64;      // bodies per simulation
 constexpr int kPatchTile = 16;      // immersed-boundary gather block: 16 x 16 patch sites
+constexpr int kMaxCand = 512;       // nodes whose footprint can reach one gather block
 constexpr int kTab = 4096;          // stiffness-table intervals over s = |P|^2 in [0, P_clamp^2]
 constexpr int kHalo = 4;            // fused kernel: polarization halo depth (stress and h use 3)
 constexpr int kDefaultShift = 10;   // FP16 storage: offsets scaled by 2^10
@@ -50,6 +51,8 @@ struct BodyDev {
                                     // (node coordinates), then x mod nx, y mod ny
     float *fib;                     // spread force patch: 2 planes ps*ps
     float *vib;                     // fluid velocity patch: 2 planes ps*ps
+    float *nw;                      // per node: the 4 x and 4 y kernel weights of its footprint
+    int *nix;                       // per node: first footprint site (unwrapped x, y)
 };
 
 // fused kernel work item: columns [x0, x0+w), rows [y0, y0+l) of one simulation

@@ -118,30 +118,22 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// One block per (body, 16x16 patch tile).  ADVANCE: move the nodes from R(t) to R(t+1) by Heun
-// with the velocity patch written during step t, then compute the forces at the new positions
-// with the pull at time *d_t; otherwise use R[cur] as it is.  Every block of a body repeats the
-// (cheap) node work; block 0 of the body stores nodes, forces and the new patch origin.
+// One block per body.  ADVANCE: move the nodes from R(t) to R(t+1) by Heun with the velocity patch
+// written during step t (App. A: overdamped, no slip); otherwise take R[cur] as it is.  Then the
+// node forces at the new positions with the pull at time *d_t, the new patch origin, and each
+// node's footprint weights for the spreading kernel.
 template <bool ADVANCE>
-__global__ __launch_bounds__(256) void k_ib(const SimDev *__restrict__ sims, BodyDev *__restrict__ bodies,
-                                            const int2 *__restrict__ blk, int cur, const int *__restrict__ d_t,
-                                            int *__restrict__ d_status) {
+__global__ __launch_bounds__(256) void k_ib_nodes(const SimDev *__restrict__ sims, BodyDev *__restrict__ bodies,
+                                                  int cur, const int *__restrict__ d_t, int *__restrict__ d_status) {
     __shared__ double2 sR[kMaxNodes];
-    __shared__ double2 sF[kMaxNodes];
-    __shared__ int4 sCand[kMaxNodes];
-    __shared__ float4 sW[kMaxNodes][2];
     __shared__ double sRed[4][4];
-    __shared__ int sCnt[4];
-    __shared__ int sTot;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int2 bt = blk[blockIdx.x];
-    const BodyDev &B = bodies[bt.x];
+    const BodyDev &B = bodies[blockIdx.x];
     const SimDev &S = sims[B.sim];
     const int n = B.n;
     const int dst = ADVANCE ? (cur ^ 1) : cur;
     bool bad = false;
 
-    // 1. positions at the new time
     const double2 *Rc = reinterpret_cast<const double2 *>(B.R[cur]);
     int ox = 0, oy = 0;
     if (ADVANCE) {
@@ -161,15 +153,27 @@ __global__ __launch_bounds__(256) void k_ib(const SimDev *__restrict__ sims, Bod
     }
     __syncthreads();
 
-    // 2. node forces and the bounding box of the nodes
     const double pf = pull_factor(B, (double)d_t[0]);
+    double2 *Fn = reinterpret_cast<double2 *>(B.fnode);
+    double2 *Rd = reinterpret_cast<double2 *>(B.R[dst]);
     double mnx = 1e300, mny = 1e300, mxx = -1e300, mxy = -1e300;
     for (int a = tid; a < n; a += 256) {
-        sF[a] = node_force(B, sR, a, pf);
-        mnx = fmin(mnx, sR[a].x);
-        mny = fmin(mny, sR[a].y);
-        mxx = fmax(mxx, sR[a].x);
-        mxy = fmax(mxy, sR[a].y);
+        const double2 R = sR[a];
+        Fn[a] = node_force(B, sR, a, pf);
+        if (ADVANCE) Rd[a] = R;
+        int ix, iy;
+        float wx[4], wy[4];
+        phi4(R.x, ix, wx);
+        phi4(R.y, iy, wy);
+        B.nix[2 * a] = ix;
+        B.nix[2 * a + 1] = iy;
+        float4 *w = reinterpret_cast<float4 *>(B.nw) + 2 * a;
+        w[0] = make_float4(wx[0], wx[1], wx[2], wx[3]);
+        w[1] = make_float4(wy[0], wy[1], wy[2], wy[3]);
+        mnx = fmin(mnx, R.x);
+        mny = fmin(mny, R.y);
+        mxx = fmax(mxx, R.x);
+        mxy = fmax(mxy, R.y);
     }
     mnx = wave_min(mnx);
     mny = wave_min(mny);
@@ -182,82 +186,94 @@ __global__ __launch_bounds__(256) void k_ib(const SimDev *__restrict__ sims, Bod
         sRed[wv][3] = mxy;
     }
     __syncthreads();
-    mnx = fmin(fmin(sRed[0][0], sRed[1][0]), fmin(sRed[2][0], sRed[3][0]));
-    mny = fmin(fmin(sRed[0][1], sRed[1][1]), fmin(sRed[2][1], sRed[3][1]));
-    mxx = fmax(fmax(sRed[0][2], sRed[1][2]), fmax(sRed[2][2], sRed[3][2]));
-    mxy = fmax(fmax(sRed[0][3], sRed[1][3]), fmax(sRed[2][3], sRed[3][3]));
-    // patch: 3 sites of margin below the lowest node covers the kernel support (2) plus one
-    // site of node motion; the same margin above is checked against the patch side
-    const int nox = (int)floor(mnx) - 3, noy = (int)floor(mny) - 3;
-    if ((int)floor(mxx) + 3 - nox >= B.ps || (int)floor(mxy) + 3 - noy >= B.ps) bad = true;
-
-    if (bt.y == 0) {
-        double2 *Rd = reinterpret_cast<double2 *>(B.R[dst]);
-        double2 *Fn = reinterpret_cast<double2 *>(B.fnode);
-        for (int a = tid; a < n; a += 256) {
-            if (ADVANCE) Rd[a] = sR[a];
-            Fn[a] = sF[a];
-        }
-        if (tid == 0) {
-            B.origin[4 * dst] = nox;
-            B.origin[4 * dst + 1] = noy;
-            B.origin[4 * dst + 2] = wrapi(nox, S.nx);
-            B.origin[4 * dst + 3] = wrapi(noy, S.ny);
-        }
+    if (tid == 0) {
+        mnx = fmin(fmin(sRed[0][0], sRed[1][0]), fmin(sRed[2][0], sRed[3][0]));
+        mny = fmin(fmin(sRed[0][1], sRed[1][1]), fmin(sRed[2][1], sRed[3][1]));
+        mxx = fmax(fmax(sRed[0][2], sRed[1][2]), fmax(sRed[2][2], sRed[3][2]));
+        mxy = fmax(fmax(sRed[0][3], sRed[1][3]), fmax(sRed[2][3], sRed[3][3]));
+        // patch: 3 sites of margin below the lowest node cover the kernel support (2) plus one
+        // site of node motion; the same margin above is checked against the patch side
+        const int nox = (int)floor(mnx) - 3, noy = (int)floor(mny) - 3;
+        if ((int)floor(mxx) + 3 - nox >= B.ps || (int)floor(mxy) + 3 - noy >= B.ps) bad = true;
+        B.origin[4 * dst] = nox;
+        B.origin[4 * dst + 1] = noy;
+        B.origin[4 * dst + 2] = wrapi(nox, S.nx);
+        B.origin[4 * dst + 3] = wrapi(noy, S.ny);
     }
+    if (bad) atomicOr(d_status, kStatusPatch);
+}
 
-    // 3. gather-spread onto this block's 16x16 tile of the patch, node order fixed
+// One block per (body, 16x16 tile of its patch): f_IB(r) = sum_a f_a phi phi (App. A) as a gather
+// over the nodes whose 4x4 footprint reaches the tile, summed in node order (deterministic).
+__global__ __launch_bounds__(256) void k_ib_spread(const BodyDev *__restrict__ bodies, const int2 *__restrict__ blk,
+                                                   int dst, int *__restrict__ d_status) {
+    __shared__ int sA[kMaxCand];
+    __shared__ int2 sI[kMaxCand];
+    __shared__ float4 sW[kMaxCand][2];
+    __shared__ double2 sF[kMaxCand];
+    __shared__ int sCnt[4];
+    __shared__ int sTot;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int2 bt = blk[blockIdx.x];
+    const BodyDev &B = bodies[bt.x];
+    const int n = B.n;
     const int tx = bt.y % B.nside, ty = bt.y / B.nside;
-    const int X0 = nox + tx * kPatchTile, Y0 = noy + ty * kPatchTile;
+    const int X0 = B.origin[4 * dst] + tx * kPatchTile, Y0 = B.origin[4 * dst + 1] + ty * kPatchTile;
     if (tid == 0) sTot = 0;
     __syncthreads();
+    bool bad = false;
     for (int base = 0; base < n; base += 256) {
-        int a = base + tid;
+        const int a = base + tid;
         bool flag = false;
+        int ix = 0, iy = 0;
         if (a < n) {
-            double2 R = sR[a];
-            flag = R.x > X0 - 2.0 && R.x < X0 + kPatchTile + 1.0 && R.y > Y0 - 2.0 && R.y < Y0 + kPatchTile + 1.0;
+            ix = B.nix[2 * a];
+            iy = B.nix[2 * a + 1];
+            flag = ix > X0 - 4 && ix < X0 + kPatchTile && iy > Y0 - 4 && iy < Y0 + kPatchTile;
         }
-        unsigned long long m = __ballot(flag);
-        int pre = __popcll(m & ((1ull << lane) - 1ull));
+        const unsigned long long m = __ballot(flag);
+        const int pre = __popcll(m & ((1ull << lane) - 1ull));
         if (lane == 0) sCnt[wv] = __popcll(m);
         __syncthreads();
         int off = sTot;
         for (int w = 0; w < wv; ++w) off += sCnt[w];
         if (flag) {
-            // candidate: its footprint origin and separable weights, relative to the tile
-            int ix, iy;
-            float wx[4], wy[4];
-            phi4(sR[a].x, ix, wx);
-            phi4(sR[a].y, iy, wy);
             const int q = off + pre;
-            sCand[q] = make_int4(a, ix - X0, iy - Y0, 0);
-            sW[q][0] = make_float4(wx[0], wx[1], wx[2], wx[3]);
-            sW[q][1] = make_float4(wy[0], wy[1], wy[2], wy[3]);
+            if (q < kMaxCand) {
+                sA[q] = a;
+                sI[q] = make_int2(ix - X0, iy - Y0);
+                const float4 *w = reinterpret_cast<const float4 *>(B.nw) + 2 * a;
+                sW[q][0] = w[0];
+                sW[q][1] = w[1];
+                sF[q] = reinterpret_cast<const double2 *>(B.fnode)[a];
+            } else {
+                bad = true;
+            }
         }
         __syncthreads();
         if (tid == 0) sTot += sCnt[0] + sCnt[1] + sCnt[2] + sCnt[3];
         __syncthreads();
     }
+    const int cnt = min(sTot, kMaxCand);
     const int lx = tid % kPatchTile, ly = tid / kPatchTile;
     const int px = tx * kPatchTile + lx, py = ty * kPatchTile + ly;
     if (px < B.ps && py < B.ps) {
         double fx = 0.0, fy = 0.0;
-        for (int q = 0; q < sTot; ++q) {
-            const int4 cq = sCand[q];
-            const int i = lx - cq.y, jj = ly - cq.z;
+        for (int q = 0; q < cnt; ++q) {
+            const int2 o = sI[q];
+            const int i = lx - o.x, jj = ly - o.y;
             if ((unsigned)i < 4u && (unsigned)jj < 4u) {
                 const float4 wxv = sW[q][0], wyv = sW[q][1];
                 const float wxs = i == 0 ? wxv.x : i == 1 ? wxv.y : i == 2 ? wxv.z : wxv.w;
                 const float wys = jj == 0 ? wyv.x : jj == 1 ? wyv.y : jj == 2 ? wyv.z : wyv.w;
                 const double w = (double)wxs * (double)wys;
-                fx += sF[cq.x].x * w;
-                fy += sF[cq.x].y * w;
+                fx += sF[q].x * w;
+                fy += sF[q].y * w;
             }
         }
-        size_t i = (size_t)py * B.ps + px;
+        const unsigned i = (unsigned)(py * B.ps + px);
         B.fib[i] = (float)fx;
-        B.fib[(size_t)B.ps * B.ps + i] = (float)fy;
+        B.fib[(unsigned)(B.ps * B.ps) + i] = (float)fy;
     }
     if (bad) atomicOr(d_status, kStatusPatch);
 }
@@ -878,13 +894,14 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ src, HT 
 // launch wrappers (host)
 // ------------------------------------------------------------------------------------------------
 
-hipError_t launch_ib(bool advance, int nblocks, hipStream_t st, const SimDev *sims, BodyDev *bodies, const int2 *blk,
-                     int cur, const int *d_t, int *d_status) {
-    if (nblocks <= 0) return hipSuccess;
+hipError_t launch_ib(bool advance, int nbodies, int ntiles, hipStream_t st, const SimDev *sims, BodyDev *bodies,
+                     const int2 *blk, int cur, const int *d_t, int *d_status) {
+    if (nbodies <= 0) return hipSuccess;
     if (advance)
-        k_ib<true><<<nblocks, 256, 0, st>>>(sims, bodies, blk, cur, d_t, d_status);
+        k_ib_nodes<true><<<nbodies, 256, 0, st>>>(sims, bodies, cur, d_t, d_status);
     else
-        k_ib<false><<<nblocks, 256, 0, st>>>(sims, bodies, blk, cur, d_t, d_status);
+        k_ib_nodes<false><<<nbodies, 256, 0, st>>>(sims, bodies, cur, d_t, d_status);
+    k_ib_spread<<<ntiles, 256, 0, st>>>(bodies, blk, advance ? (cur ^ 1) : cur, d_status);
     return hipGetLastError();
 }
 

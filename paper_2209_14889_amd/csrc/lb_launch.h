@@ -6,8 +6,8 @@
 
 namespace lbk {
 
-hipError_t launch_ib(bool advance, int nblocks, hipStream_t st, const SimDev *sims, BodyDev *bodies, const int2 *blk,
-                     int cur, const int *d_t, int *d_status);
+hipError_t launch_ib(bool advance, int nbodies, int ntiles, hipStream_t st, const SimDev *sims, BodyDev *bodies,
+                     const int2 *blk, int cur, const int *d_t, int *d_status);
 hipError_t launch_fused(int T, bool fp16, int grid, hipStream_t st, const SimDev *sims, const BodyDev *bodies,
                         const WorkItem *items, int n_items, int cur, int *d_t);
 // resident fused work-groups per compute unit for work-group size T
