@@ -133,6 +133,10 @@ int lb_read_fields(lb_handle *h, int32_t sim, uint32_t field_mask, double *host_
  * out[6..7] total force the nodes apply to the fluid (sum_a f_a). */
 int lb_body_force(lb_handle *h, int32_t sim, int32_t body, double out[8]);
 
+/* lb_body_force for every body of every simulation at once (simulations in order, bodies in
+ * order within each): 8 doubles per body into host_out (capacity n_out doubles).  Synchronous. */
+int lb_body_forces(lb_handle *h, double *host_out, size_t n_out);
+
 /* FP64 conservation sums of simulation `sim` at the current time (synchronous):
  * out[0] = sum rho, out[1..2] = sum of sum_n c_n h_n (momentum without the half force). */
 int lb_conservation(lb_handle *h, int32_t sim, double out[3]);

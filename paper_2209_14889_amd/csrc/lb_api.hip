@@ -162,7 +162,7 @@ struct Plan {
     std::vector<BodyPlan> bodies;
     std::vector<double> clamps;
     std::vector<size_t> oTab;
-    size_t oSims, oBodies, oItems, oIbBlk, oSiteBlk, oT, oStatus, oPartial, oOut, oStage;
+    size_t oSims, oBodies, oItems, oIbBlk, oSiteBlk, oT, oStatus, oPartial, oOut, oOutAll, oStage;
     std::vector<WorkItem> items;
     std::vector<int2> ib_blk;
     std::vector<SiteBlock> site_blk;
@@ -323,6 +323,7 @@ Plan make_plan(const lb_sim_params *sims, int n_sims, const Opt &o) {
     pl.max_partial = 1024;
     pl.oPartial = a.take(sizeof(double) * 3 * pl.max_partial);
     pl.oOut = a.take(sizeof(double) * 16);
+    pl.oOutAll = a.take(sizeof(double) * 6 * std::max(1, total_bodies));
     pl.oStage = a.take(10 * maxN * 4);
     pl.bytes = a.off + 256;
     return pl;
@@ -387,6 +388,7 @@ struct lb_handle {
     int *d_status = nullptr;
     double *d_partial = nullptr;
     double *d_out = nullptr;
+    double *d_out_all = nullptr;
     float *d_stage = nullptr;
     int64_t t = 0;
     int cur = 0;
@@ -632,6 +634,10 @@ int build_graph(lb_handle *h) {
 
 }  // namespace
 
+namespace lbk {
+void set_last_error(const char *msg) { g_err = msg; }
+}  // namespace lbk
+
 extern "C" {
 
 const char *lb_last_error(void) { return g_err.c_str(); }
@@ -695,6 +701,7 @@ static int create_impl(const lb_sim_params *sims, int n_sims, const lb_options *
     h->d_status = A.ptr<int>(pl.oStatus);
     h->d_partial = A.ptr<double>(pl.oPartial);
     h->d_out = A.ptr<double>(pl.oOut);
+    h->d_out_all = A.ptr<double>(pl.oOutAll);
     h->d_stage = A.ptr<float>(pl.oStage);
 
     // simulation descriptors and initial fields
@@ -974,18 +981,7 @@ int lb_read_fields(lb_handle *h, int32_t sim, uint32_t mask, double *out, size_t
     }
 }
 
-int lb_body_force(lb_handle *h, int32_t sim, int32_t body, double out[8]) {
-    if (!h || !out) return fail(LB_EINVAL, "NULL argument");
-    if (sim < 0 || sim >= h->n_sims) return fail(LB_ERANGE, "sim index out of range");
-    if (body < 0 || body >= h->params[sim].n_bodies) return fail(LB_ERANGE, "body index out of range");
-    int rc = check_status(h);
-    if (rc) return rc;
-    const int bi = h->hs[sim].b0 + body;
-    HIPCHK(launch_body_force(h->stream, h->d_sims, h->d_bodies, bi, h->cur, h->d_out));
-    double r[6];
-    HIPCHK(hipMemcpyAsync(r, h->d_out, sizeof r, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
-    const BodyDev &B = h->hb[bi];
+static void body_out(const lb_handle *h, const BodyDev &B, const double *r, double *out) {
     double pf = 1.0;
     if (B.width > 0.0) {
         double t = (double)h->t;
@@ -999,6 +995,35 @@ int lb_body_force(lb_handle *h, int32_t sim, int32_t body, double out[8]) {
     out[5] = r[3];
     out[6] = r[4];
     out[7] = r[5];
+}
+
+int lb_body_force(lb_handle *h, int32_t sim, int32_t body, double out[8]) {
+    if (!h || !out) return fail(LB_EINVAL, "NULL argument");
+    if (sim < 0 || sim >= h->n_sims) return fail(LB_ERANGE, "sim index out of range");
+    if (body < 0 || body >= h->params[sim].n_bodies) return fail(LB_ERANGE, "body index out of range");
+    int rc = check_status(h);
+    if (rc) return rc;
+    const int bi = h->hs[sim].b0 + body;
+    HIPCHK(launch_body_force(h->stream, h->d_sims, h->d_bodies, bi, 1, h->cur, h->d_out_all));
+    double r[6];
+    HIPCHK(hipMemcpyAsync(r, h->d_out_all, sizeof r, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    body_out(h, h->hb[bi], r, out);
+    return check_status(h);
+}
+
+int lb_body_forces(lb_handle *h, double *out, size_t n_out) {
+    if (!h || !out) return fail(LB_EINVAL, "NULL argument");
+    const size_t nb = h->hb.size();
+    if (n_out < 8 * nb) return fail(LB_ERANGE, "output buffer too small");
+    if (nb == 0) return LB_OK;
+    int rc = check_status(h);
+    if (rc) return rc;
+    HIPCHK(launch_body_force(h->stream, h->d_sims, h->d_bodies, 0, (int)nb, h->cur, h->d_out_all));
+    std::vector<double> r(6 * nb);
+    HIPCHK(hipMemcpyAsync(r.data(), h->d_out_all, sizeof(double) * 6 * nb, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (size_t b = 0; b < nb; ++b) body_out(h, h->hb[b], r.data() + 6 * b, out + 8 * b);
     return check_status(h);
 }
 

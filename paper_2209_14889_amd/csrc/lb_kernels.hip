@@ -814,10 +814,11 @@ __global__ __launch_bounds__(64) void k_sums_final(const SimDev *__restrict__ si
 // body observables: restoring force (sum of div sigma over sites inside the node polygon),
 // centre of mass, total node force; one 256-thread block
 __global__ __launch_bounds__(256) void k_body_force(const SimDev *__restrict__ sims, const BodyDev *__restrict__ bodies,
-                                                    int body, int cur, double *__restrict__ out) {
+                                                    int body0, int cur, double *__restrict__ out_all) {
     __shared__ double2 sR[kMaxNodes];
     __shared__ double sh[8][4];
-    const BodyDev &B = bodies[body];
+    const BodyDev &B = bodies[body0 + blockIdx.x];
+    double *out = out_all + 6 * blockIdx.x;
     const SimDev &S = sims[B.sim];
     const int n = B.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const double2 *R = reinterpret_cast<const double2 *>(B.R[cur]);
@@ -967,8 +968,10 @@ hipError_t launch_sums(bool fp16, int sim, int nblocks, hipStream_t st, const Si
     return hipGetLastError();
 }
 
-hipError_t launch_body_force(hipStream_t st, const SimDev *sims, const BodyDev *bodies, int body, int cur, double *out) {
-    k_body_force<<<1, 256, 0, st>>>(sims, bodies, body, cur, out);
+hipError_t launch_body_force(hipStream_t st, const SimDev *sims, const BodyDev *bodies, int body0, int nbodies, int cur,
+                             double *out) {
+    if (nbodies <= 0) return hipSuccess;
+    k_body_force<<<nbodies, 256, 0, st>>>(sims, bodies, body0, cur, out);
     return hipGetLastError();
 }
 

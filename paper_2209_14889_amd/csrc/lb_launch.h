@@ -6,6 +6,9 @@
 
 namespace lbk {
 
+// message returned by lb_last_error() on this thread
+void set_last_error(const char *msg);
+
 hipError_t launch_ib(bool advance, int nbodies, int ntiles, hipStream_t st, const SimDev *sims, BodyDev *bodies,
                      const int2 *blk, int cur, const int *d_t, int *d_status);
 hipError_t launch_fused(int T, bool fp16, int grid, hipStream_t st, const SimDev *sims, const BodyDev *bodies,
@@ -18,7 +21,8 @@ hipError_t launch_readout(bool fp16, int nblocks, int block0, hipStream_t st, co
                           const BodyDev *bodies, const SiteBlock *blk, int cur, float *out);
 hipError_t launch_sums(bool fp16, int sim, int nblocks, hipStream_t st, const SimDev *sims, int cur, double *partial,
                        double *out, double check_mass, int *d_status);
-hipError_t launch_body_force(hipStream_t st, const SimDev *sims, const BodyDev *bodies, int body, int cur,
+// body observables of bodies body0 .. body0+nbodies-1, 6 doubles each into out
+hipError_t launch_body_force(hipStream_t st, const SimDev *sims, const BodyDev *bodies, int body0, int nbodies, int cur,
                              double *out);
 hipError_t launch_pack(bool fp16, hipStream_t st, const float *src, void *dst, size_t n, float scale);
 

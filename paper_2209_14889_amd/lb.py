@@ -81,6 +81,7 @@ def lib():
         L.lb_read_fields.argtypes = [vp, ctypes.c_int32, ctypes.c_uint32, _dp, ctypes.c_size_t]
         L.lb_body_force.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, _dp]
         L.lb_conservation.argtypes = [vp, ctypes.c_int32, _dp]
+        L.lb_body_forces.argtypes = [vp, _dp, ctypes.c_size_t]
         L.lb_sync.argtypes = [vp]
         L.lb_time.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
         L.lb_timing.argtypes = [vp, _dp, ctypes.POINTER(ctypes.c_int64), _dp, ctypes.POINTER(ctypes.c_int64),
@@ -90,7 +91,8 @@ def lib():
                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _dp]
         L.lb_last_error.restype = ctypes.c_char_p
         for name in ("lb_query_arena_bytes", "lb_create", "lb_step", "lb_read_fields", "lb_body_force",
-                     "lb_conservation", "lb_sync", "lb_time", "lb_timing", "lb_destroy", "lb_launch_shape"):
+                     "lb_conservation", "lb_sync", "lb_time", "lb_timing", "lb_destroy", "lb_launch_shape",
+                     "lb_body_forces"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -234,6 +236,13 @@ class Sim:
         out = np.empty(8)
         check(lib().lb_body_force(self.h, sim, body, out.ctypes.data_as(_dp)))
         return dict(restoring=out[0:2].copy(), pull=out[2:4].copy(), com=out[4:6].copy(), node_force=out[6:8].copy())
+
+    def body_forces(self) -> np.ndarray:
+        """(total bodies, 8): restoring force (2), pull (2), centre of mass (2), node force (2)."""
+        nb = sum(len(s.bodies) for s in self.specs)
+        out = np.empty(8 * max(1, nb))
+        check(lib().lb_body_forces(self.h, out.ctypes.data_as(_dp), out.size))
+        return out[:8 * nb].reshape(nb, 8).copy()
 
     def conservation(self, sim: int = 0) -> np.ndarray:
         out = np.empty(3)

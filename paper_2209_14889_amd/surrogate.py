@@ -1,0 +1,213 @@
+"""Learned surrogate of the body's restoring-force time series, with the lattice Boltzmann run as
+fallback and as judge of its error.
+
+Inputs (5): stress diffusion D_p, relaxation time, body radius, director angle to the pull, and
+polarization magnitude P_eq (alpha = -P_eq^2).  Output: the restoring force along the pull (the sum
+of div sigma^p over the sites inside the body, Figs. 5, 6, 10) sampled every 64 steps of a 4096-step
+pull-and-release run on a 128 x 128 lattice (64 samples).
+
+Training data comes from batched LB ensembles run by the library; the networks (an ensemble of M
+members with different seeds) are trained by the library's own forward/backward/Adam kernels.  The
+spread of the members estimates the error of their mean; rows whose estimate exceeds the threshold
+are simulated instead.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import lb, mlp
+from . import workload as wl
+
+WIDTHS = [5, 256, 256, 256, 64]
+
+
+def features(inputs) -> np.ndarray:
+    """Map the five parameters to [-1, 1]."""
+    x = []
+    for d in inputs:
+        x.append([
+            math.log(d["D_p"] / 0.001) / math.log(200.0),
+            math.log(d["relax"] / 20.0) / math.log(20.0),
+            (d["radius"] - 4.0) / 12.0,
+            d["theta0"] / (math.pi / 2),
+            d["P_eq"] / 0.95,
+        ])
+    return (2.0 * np.asarray(x, dtype=np.float64) - 1.0).astype(np.float32)
+
+
+def simulate(seeds, batch: int = 512, n: int = wl.C5_N, steps: int = wl.C5_STEPS,
+             every: int = wl.C5_SAMPLE_EVERY, log=None):
+    """Run the LB method for the given seeds in batched ensembles; returns (inputs, series)
+    with series[i, k] the restoring force along +x after (k+1)*every steps."""
+    seeds = list(seeds)
+    inputs, series = [], []
+    for c0 in range(0, len(seeds), batch):
+        chunk = seeds[c0:c0 + batch]
+        specs = [wl.surrogate_member(s, n) for s in chunk]
+        sim = lb.Sim(specs, lb.make_options(graph_chunk=every if every % 2 == 0 else 0))
+        Y = np.empty((len(chunk), steps // every))
+        for k in range(steps // every):
+            sim.step(every)
+            Y[:, k] = sim.body_forces()[:, 0]
+        sim.close()
+        inputs += [s.meta for s in specs]
+        series.append(Y)
+        if log:
+            log(f"surrogate: simulated {c0 + len(chunk)}/{len(seeds)} runs")
+    return inputs, np.concatenate(series)
+
+
+class Surrogate:
+    def __init__(self, members: int = 4, widths=WIDTHS, seed: int = 0, max_batch: int = 4096,
+                 device: str = "cuda:0"):
+        import torch
+        self.torch = torch
+        self.widths = list(widths)
+        self.device = device
+        self.nets = [mlp.MLP(widths, max_batch, device) for _ in range(members)]
+        for i, net in enumerate(self.nets):
+            net.set_params(mlp.init_params(widths, seed + 1000 * i))
+        self.scale = 1.0
+        self.threshold = 0.02
+
+    def _t(self, a):
+        return self.torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=self.device)
+
+    def fit(self, X, Y, epochs: int = 1500, batch: int = 512, lr: float = 2e-3, lr_min: float = 2e-5,
+            seed: int = 0, log=None):
+        """Adam with cosine learning-rate decay on the mean squared relative error of each series."""
+        self.scale = float(np.sqrt(np.mean(np.asarray(Y) ** 2)))
+        Xt, Yt = self._t(X), self._t(np.asarray(Y) / self.scale)
+        n = Xt.shape[0]
+        rng = np.random.default_rng(seed)
+        steps_per_epoch = max(1, n // batch)
+        total = epochs * steps_per_epoch
+        loss = self.torch.zeros(1, dtype=self.torch.float32, device=self.device)
+        self.torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for m, net in enumerate(self.nets):
+            step = 0
+            for ep in range(epochs):
+                perm = self.torch.as_tensor(rng.permutation(n)[:steps_per_epoch * batch], device=self.device)
+                Xe, Ye = Xt[perm].contiguous(), Yt[perm].contiguous()
+                self.torch.cuda.synchronize()
+                for b in range(steps_per_epoch):
+                    lr_t = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * step / total))
+                    net.train_step(Xe[b * batch:(b + 1) * batch], Ye[b * batch:(b + 1) * batch], lr_t, loss)
+                    step += 1
+                net.stream.synchronize()
+                if log and (ep + 1) % max(1, epochs // 5) == 0:
+                    log(f"surrogate: member {m} epoch {ep + 1}/{epochs} batch loss {float(loss.item()):.3e}")
+        self.torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def predict(self, X):
+        """Ensemble mean, and the relative spread |std| / |mean| of each row (the error estimate)."""
+        Xt = self._t(X)
+        outs = np.stack([net.forward(Xt).cpu().numpy() for net in self.nets]) * self.scale
+        mean = outs.mean(axis=0)
+        spread = np.linalg.norm(outs.std(axis=0), axis=1) / np.maximum(np.linalg.norm(mean, axis=1), 1e-300)
+        return mean, spread
+
+    def calibrate(self, X, Y, target: float = 0.02, quantile: float = 0.95):
+        """Largest threshold on the spread whose accepted validation rows keep the given quantile
+        of their true relative error at or below target (falls back to 0: simulate everything)."""
+        mean, spread = self.predict(X)
+        err = np.linalg.norm(mean - Y, axis=1) / np.linalg.norm(Y, axis=1)
+        best = 0.0
+        for th in np.sort(spread):
+            acc = spread <= th
+            if acc.sum() >= 5 and np.quantile(err[acc], quantile) <= target:
+                best = float(th)
+        self.threshold = best
+        return best
+
+    def predict_with_fallback(self, seeds, X=None, batch: int = 512, **sim_kw):
+        """Surrogate rows where the spread is at most the threshold; LB for the rest."""
+        seeds = list(seeds)
+        if X is None:
+            X = features([wl.surrogate_inputs(s) for s in seeds])
+        t0 = time.perf_counter()
+        mean, spread = self.predict(X)
+        t_inf = time.perf_counter() - t0
+        fb = np.nonzero(spread > self.threshold)[0]
+        out = mean.copy()
+        t1 = time.perf_counter()
+        if fb.size:
+            _, Yfb = simulate([seeds[i] for i in fb], batch=batch, **sim_kw)
+            out[fb] = Yfb
+        t_lb = time.perf_counter() - t1
+        return out, dict(fallback=fb, t_inference=t_inf, t_fallback=t_lb, spread=spread)
+
+
+def main(argv=None):
+    """Full surrogate study: 4096 LB runs for training (the last 512 held back to calibrate the
+    threshold), 512 held-out runs for the error and the speedup; prints one JSON line."""
+    import argparse
+    import json
+    import sys
+
+    import torch
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=4096)
+    ap.add_argument("--test", type=int, default=512)
+    ap.add_argument("--val", type=int, default=512)
+    ap.add_argument("--members", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=600)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--sim-batch", type=int, default=1024)
+    ap.add_argument("--target", type=float, default=0.02)
+    ap.add_argument("--out", default="")
+    a = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    inp, Y = simulate(range(3000, 3000 + a.train), batch=a.sim_batch, log=log)
+    t_data = time.perf_counter() - t0
+    X = features(inp)
+    ntr = a.train - a.val
+    s = Surrogate(members=a.members, max_batch=max(a.batch, a.test, a.val))
+    t_fit = s.fit(X[:ntr], Y[:ntr], epochs=a.epochs, batch=a.batch, lr=a.lr, log=log)
+    th = s.calibrate(X[ntr:], Y[ntr:], target=a.target)
+    log(f"surrogate: threshold {th:.4g} on the spread")
+
+    seeds = list(range(9000, 9000 + a.test))
+    Xt = features([wl.surrogate_inputs(x) for x in seeds])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, Yt = simulate(seeds, batch=a.test)
+    t_lb = time.perf_counter() - t1
+    s.predict(Xt)   # first call pays one-off costs
+    out, info = s.predict_with_fallback(seeds, Xt, batch=a.test)
+    mean, _ = s.predict(Xt)
+    err = np.linalg.norm(out - Yt, axis=1) / np.linalg.norm(Yt, axis=1)
+    err_nn = np.linalg.norm(mean - Yt, axis=1) / np.linalg.norm(Yt, axis=1)
+    t_sur = info["t_inference"] + info["t_fallback"]
+    res = dict(
+        train_runs=a.train, held_out_runs=a.test, members=a.members, widths=s.widths,
+        t_lb_data_s=round(t_data, 3), t_fit_s=round(t_fit, 3), threshold=th,
+        t_lb_all_s=round(t_lb, 4), t_inference_s=round(info["t_inference"], 5),
+        t_fallback_s=round(info["t_fallback"], 4), n_fallback=int(info["fallback"].size),
+        speedup=round(t_lb / t_sur, 2),
+        err_with_fallback=dict(mean=float(err.mean()), p95=float(np.quantile(err, 0.95)), max=float(err.max()),
+                               frac_le_target=float(np.mean(err <= a.target))),
+        err_network_only=dict(mean=float(err_nn.mean()), p95=float(np.quantile(err_nn, 0.95)),
+                              max=float(err_nn.max()), frac_le_target=float(np.mean(err_nn <= a.target))),
+    )
+    line = json.dumps(res)
+    print(line, flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(line + "\n")
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,83 @@
+"""The C-ABI library loads without a GPU, exports every function its headers declare, and rejects
+invalid descriptions in its host-side validation (no device call is made by these entry points)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2209_14889_amd import lb, mlp
+from paper_2209_14889_amd import workload as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = ["include/lb.h", "include/lb_mlp.h"]
+
+
+def declared_functions():
+    names = []
+    for h in HEADERS:
+        text = open(os.path.join(ROOT, h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w \*]*?\b(lb_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_headers_declare_the_boundary():
+    names = declared_functions()
+    for n in ("lb_create", "lb_step", "lb_read_fields", "lb_body_force", "lb_destroy", "lb_mlp_forward",
+              "lb_mlp_train_step"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = lb.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def _query(specs, opt=None):
+    m = lb._Marshal(specs)
+    n = ctypes.c_size_t(0)
+    rc = lb.lib().lb_query_arena_bytes(m.params, len(specs), ctypes.byref(opt) if opt else None, ctypes.byref(n))
+    return rc, int(n.value)
+
+
+def test_query_arena_bytes_scales_with_the_lattice():
+    small = wl.small_case(3, 48, 40).sims
+    big = wl.small_case(3, 96, 80).sims
+    rc1, b1 = _query(small)
+    rc2, b2 = _query(big)
+    assert rc1 == lb.LB_OK and rc2 == lb.LB_OK
+    assert b2 > 3 * b1 > 0
+    rc3, b3 = _query(small, lb.make_options(precision=1))
+    assert rc3 == lb.LB_OK and b3 < b1          # FP16 populations take less memory
+
+
+@pytest.mark.parametrize("bad", ["tau", "nx", "nodes", "P_clamp", "precision"])
+def test_validation_rejects_invalid_input(bad):
+    spec = wl.small_case(3, 48, 40).sims[0]
+    opt = None
+    if bad == "tau":
+        spec.params["tau"] = 0.5
+    elif bad == "nx":
+        spec.nx = 0
+    elif bad == "nodes":
+        spec.bodies[0].R = np.zeros((2000, 2))
+    elif bad == "P_clamp":
+        spec.params["P_clamp"] = 1.5
+    elif bad == "precision":
+        opt = lb.make_options(precision=7)
+    rc, _ = _query([spec], opt)
+    assert rc != lb.LB_OK
+    assert lb.lib().lb_last_error().decode()
+
+
+def test_mlp_sizes_are_host_side():
+    w = [5, 256, 256, 256, 64]
+    assert mlp.n_params(w) == sum(w[i] * w[i + 1] + w[i + 1] for i in range(4))
+    n = ctypes.c_size_t(0)
+    assert mlp.lib().lb_mlp_query_bytes(ctypes.byref(mlp.make_config(w, 512)), ctypes.byref(n)) == lb.LB_OK
+    assert n.value > 4 * 4 * mlp.n_params(w)   # params, grads and two moments at least
+    bad = mlp.make_config([5, 0, 64], 512)
+    assert mlp.lib().lb_mlp_query_bytes(ctypes.byref(bad), ctypes.byref(n)) != lb.LB_OK

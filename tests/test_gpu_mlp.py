@@ -1,0 +1,162 @@
+"""Surrogate network kernels on the GPU against the FP64 oracle network.
+
+Tolerances.  The library rounds both operands of every product to BF16 (8-bit significand, relative
+rounding error <= 2^-9) and accumulates in FP32.  Against the oracle taking the SAME BF16-rounded
+operands in FP64, only FP32 accumulation order, tanhf and rare ties that round differently in FP32
+and FP64 upstream remain: 2e-3 relative L2 per array.  Against the unrounded oracle the operand
+rounding itself shows: about sqrt(2) 2^-9 per product, compounding over four layers, well inside
+3e-2 relative L2."""
+import numpy as np
+import pytest
+
+import oracle.mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+WIDTHS = [5, 256, 256, 256, 64]
+
+
+def bf16(a):
+    import torch
+    return torch.from_numpy(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def _data(seed, B, widths=WIDTHS):
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-1, 1, size=(B, widths[0])).astype(np.float32)
+    t = np.linspace(0, 1, widths[-1])
+    Y = (np.sin(np.outer(1 + X[:, 0], 3 * t) + X[:, 1:2]) * (1.5 + X[:, 2:3]) + 0.3 * X[:, 3:4] * X[:, 4:5])
+    return X, Y.astype(np.float32)
+
+
+@pytest.mark.parametrize("M,N,K", [(200, 130, 70), (64, 64, 16), (1, 5, 3), (333, 256, 5)])
+def test_gemm_bf16_matches_rounded_product(M, N, K):
+    import torch
+    from paper_2209_14889_amd import mlp
+    rng = np.random.default_rng(M * 7 + N * 3 + K)
+    A = rng.standard_normal((M, K)).astype(np.float32)
+    B = rng.standard_normal((K, N)).astype(np.float32)
+    D = mlp.gemm_bf16(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda())
+    torch.cuda.synchronize()
+    ref = bf16(A) @ bf16(B)
+    scale = np.abs(bf16(A)) @ np.abs(bf16(B))
+    # FP32 accumulation of K exact BF16 x BF16 products: error <= K 2^-24 sum |a b|
+    assert np.all(np.abs(D.cpu().numpy() - ref) <= K * 2.0 ** -24 * scale + 1e-30)
+
+
+def _net(params, B=512):
+    from paper_2209_14889_amd import mlp
+    net = mlp.MLP(WIDTHS, B)
+    net.set_params(params)
+    return net
+
+
+def test_forward_matches_oracle():
+    import torch
+    from paper_2209_14889_amd import mlp
+    params = mlp.init_params(WIDTHS, 11)
+    rng, o = np.random.default_rng(4), 0
+    for l in range(4):          # non-zero biases
+        o += WIDTHS[l + 1] * WIDTHS[l]
+        params[o:o + WIDTHS[l + 1]] = rng.uniform(-0.1, 0.1, WIDTHS[l + 1])
+        o += WIDTHS[l + 1]
+    X, _ = _data(5, 300)
+    net = _net(params)
+    Y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+    assert Y.shape == (300, 64)
+    assert rel(Y, omlp.forward(params, WIDTHS, X, bf16)[-1]) < 2e-3
+    assert rel(Y, omlp.forward(params, WIDTHS, X)[-1]) < 3e-2
+    assert np.array_equal(net.get_params(), params)
+    net.close()
+
+
+def test_gradients_match_oracle():
+    import torch
+    from paper_2209_14889_amd import mlp
+    params = mlp.init_params(WIDTHS, 12)
+    X, Y = _data(6, 257)
+    net = _net(params)
+    loss, g = net.gradients(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda())
+    g_ref = omlp.gradients(params, WIDTHS, X, Y, bf16)
+    g_full = omlp.gradients(params, WIDTHS, X, Y)
+    o = 0
+    for l in range(4):
+        for n in (WIDTHS[l + 1] * WIDTHS[l], WIDTHS[l + 1]):
+            assert rel(g[o:o + n], g_ref[o:o + n]) < 2e-3, (l, n)
+            assert rel(g[o:o + n], g_full[o:o + n]) < 3e-2, (l, n)
+            o += n
+    assert abs(loss - omlp.loss(params, WIDTHS, X, Y)) < 3e-2 * omlp.loss(params, WIDTHS, X, Y)
+    # deterministic: the same call gives the same bits
+    loss2, g2 = net.gradients(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda())
+    assert loss2 == loss and np.array_equal(g2, g)
+    net.close()
+
+
+def test_first_adam_step_follows_its_definition():
+    import torch
+    from paper_2209_14889_amd import mlp
+    params = mlp.init_params(WIDTHS, 13)
+    X, Y = _data(7, 128)
+    net = _net(params)
+    Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    _, g = net.gradients(Xd, Yd)
+    lr = 1e-3
+    net.train_step(Xd, Yd, lr)
+    p1 = net.get_params()
+    # step 1 with bias correction: m_hat = g, v_hat = g^2
+    g64 = g.astype(np.float64)
+    expect = params - lr * g64 / (np.abs(g64) + 1e-8)
+    assert np.max(np.abs(p1 - expect)) < 1e-6
+    net.close()
+
+
+def test_training_reduces_the_loss():
+    import torch
+    from paper_2209_14889_amd import mlp
+    X, Y = _data(8, 1024)
+    net = _net(mlp.init_params(WIDTHS, 14), 256)
+    Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    l0, _ = net.gradients(Xd[:256], Yd[:256])
+    for it in range(400):
+        b = (it % 4) * 256
+        net.train_step(Xd[b:b + 256], Yd[b:b + 256], 1e-3)
+    net.stream.synchronize()
+    l1, _ = net.gradients(Xd[:256], Yd[:256])
+    assert l1 < 0.05 * l0, (l0, l1)
+    net.close()
+
+
+def test_rejects_oversized_batch():
+    import torch
+    from paper_2209_14889_amd import lb
+    net = _net(np.zeros(sum(WIDTHS[i] * WIDTHS[i + 1] + WIDTHS[i + 1] for i in range(4)), np.float32), 64)
+    with pytest.raises(lb.LBError):
+        net.forward(torch.zeros((65, 5), device="cuda"))
+    net.close()
+
+
+def test_surrogate_pipeline_small():
+    """End to end at reduced size (64^2 lattices, 1024 steps, 16 samples): LB data from batched
+    ensembles, an ensemble of networks trained by the library, and the fallback rule: rows over the
+    threshold are the LB's own values, bit for bit."""
+    from paper_2209_14889_amd import surrogate as sg
+    kw = dict(n=64, steps=1024, every=64)
+    train = list(range(3000, 3096))
+    test = list(range(9000, 9016))
+    inp, Y = sg.simulate(train, batch=48, **kw)
+    assert Y.shape == (96, 16) and np.all(np.isfinite(Y))
+    assert np.abs(Y).max() > 0
+    s = sg.Surrogate(members=2, widths=[5, 64, 64, 16], max_batch=96)
+    s.fit(sg.features(inp), Y, epochs=40, batch=32)
+    th = s.calibrate(sg.features(inp[:48]), Y[:48])
+    assert th >= 0.0
+    s.threshold = float(np.median(s.predict(sg.features([sg.wl.surrogate_inputs(x) for x in test]))[1]))
+    out, info = s.predict_with_fallback(test, batch=16, **kw)
+    fb = info["fallback"]
+    assert 0 < fb.size < len(test)
+    _, Yt = sg.simulate(test, batch=16, **kw)
+    assert np.array_equal(out[fb], Yt[fb])
