@@ -6,6 +6,10 @@ Prints ONE JSON line with MLUPS (whole job), the roofline of the dominant kernel
 kernel, HBM-bound, algorithmic bytes / launch duration measured with HIP events on the library's
 stream) and the FP64 CPU oracle timed on a bounded sample of the same workload.
 
+After the field-kernel roofline, the surrogate leg trains the network ensemble on 4096 LB runs of
+128 x 128 and reports its held-out error and its speedup over the batched LB at a 2% error bound
+(the "surrogate" object of the JSON line).
+
 Default workload: the HBM-bound precision form, 2048 x 2048 periodic with 8 bodies (radius 12-24)
 and FP16 population offsets (FP32 arithmetic).  --workload c2 runs the 512 x 512 single FP32
 simulation (cache-resident), c4 the 256-simulation ensemble.
@@ -120,6 +124,8 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the surrogate leg (4096 + 512 LB runs of 128^2, network training, fallback)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB device buffer 5 times (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -182,6 +188,14 @@ def main():
     log(f"bench: field kernel {avg_ms * 1e3:.2f} us/launch, body kernel {ib_ms * 1e3:.2f} us/launch, "
         f"{achieved:.0f} GB/s algorithmic")
 
+    sur = None
+    if not args.no_surrogate:
+        from paper_2209_14889_amd import surrogate
+        log("bench: surrogate study (LB data, ensemble training, held-out error and speedup)")
+        sur = surrogate.study(log=log)
+        log(f"bench: surrogate speedup {sur['speedup']}x, held-out error with fallback "
+            f"max {sur['err_with_fallback']['max']:.4f}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on the host")
@@ -211,6 +225,7 @@ def main():
                      "traffic_unit": "GB per launch", "algorithmic_gb_per_launch": round(bps * sites / 1e9, 4),
                      "kernel": "k_fused", "bytes_per_site": bps, "launch_us": round(avg_ms * 1e3, 3)},
         "cpu_baseline": cpu,
+        "surrogate": sur,
     }
     print(json.dumps(line), flush=True)
 

@@ -2,9 +2,11 @@
 fallback and as judge of its error.
 
 Inputs (5): stress diffusion D_p, relaxation time, body radius, director angle to the pull, and
-polarization magnitude P_eq (alpha = -P_eq^2).  Output: the restoring force along the pull (the sum
-of div sigma^p over the sites inside the body, Figs. 5, 6, 10) sampled every 64 steps of a 4096-step
-pull-and-release run on a 128 x 128 lattice (64 samples).
+polarization magnitude P_eq (alpha = -P_eq^2).  Output: the distance trajectory of the body (its
+centre-of-mass displacement along the pull, the quantity of Fig. 5) sampled every 64 steps of a 4096-step pull-and-release run on a 128 x 128 lattice
+(64 samples).  The restoring force along the pull (the sum of div sigma^p over the sites inside the
+body) is recorded too, but it jumps whenever a site crosses the body outline, which no smooth map of
+the five inputs can follow to a few per cent; the displacement integrates it and is smooth.
 
 Training data comes from batched LB ensembles run by the library; the networks (an ensemble of M
 members with different seeds) are trained by the library's own forward/backward/Adam kernels.  The
@@ -39,25 +41,34 @@ def features(inputs) -> np.ndarray:
 
 
 def simulate(seeds, batch: int = 512, n: int = wl.C5_N, steps: int = wl.C5_STEPS,
-             every: int = wl.C5_SAMPLE_EVERY, log=None):
-    """Run the LB method for the given seeds in batched ensembles; returns (inputs, series)
-    with series[i, k] the restoring force along +x after (k+1)*every steps."""
+             every: int = wl.C5_SAMPLE_EVERY, observable: str = "distance", log=None):
+    """Run the LB method for the given seeds in batched ensembles; returns (inputs, series) with
+    series[i, k] the observable after (k+1)*every steps: "distance" (centre-of-mass displacement
+    along +x), "force" (restoring force along +x), or "both" (a dict of the two)."""
     seeds = list(seeds)
-    inputs, series = [], []
+    inputs, dist, force = [], [], []
     for c0 in range(0, len(seeds), batch):
         chunk = seeds[c0:c0 + batch]
         specs = [wl.surrogate_member(s, n) for s in chunk]
         sim = lb.Sim(specs, lb.make_options(graph_chunk=every if every % 2 == 0 else 0))
-        Y = np.empty((len(chunk), steps // every))
+        x0 = sim.body_forces()[:, 4]
+        D = np.empty((len(chunk), steps // every))
+        F = np.empty_like(D)
         for k in range(steps // every):
             sim.step(every)
-            Y[:, k] = sim.body_forces()[:, 0]
+            bf = sim.body_forces()
+            D[:, k] = bf[:, 4] - x0
+            F[:, k] = bf[:, 0]
         sim.close()
         inputs += [s.meta for s in specs]
-        series.append(Y)
+        dist.append(D)
+        force.append(F)
         if log:
             log(f"surrogate: simulated {c0 + len(chunk)}/{len(seeds)} runs")
-    return inputs, np.concatenate(series)
+    D, F = np.concatenate(dist), np.concatenate(force)
+    if observable == "both":
+        return inputs, dict(distance=D, force=F)
+    return inputs, (D if observable == "distance" else F)
 
 
 class Surrogate:
@@ -108,13 +119,14 @@ class Surrogate:
         """Ensemble mean, and the relative spread |std| / |mean| of each row (the error estimate)."""
         Xt = self._t(X)
         outs = np.stack([net.forward(Xt).cpu().numpy() for net in self.nets]) * self.scale
-        mean = outs.mean(axis=0)
+        mean = outs.astype(np.float64).mean(axis=0)
         spread = np.linalg.norm(outs.std(axis=0), axis=1) / np.maximum(np.linalg.norm(mean, axis=1), 1e-300)
         return mean, spread
 
-    def calibrate(self, X, Y, target: float = 0.02, quantile: float = 0.95):
+    def calibrate(self, X, Y, target: float = 0.02, quantile: float = 1.0):
         """Largest threshold on the spread whose accepted validation rows keep the given quantile
-        of their true relative error at or below target (falls back to 0: simulate everything)."""
+        (default: all of them) of their true relative error at or below target (0 when none does:
+        then every row is simulated)."""
         mean, spread = self.predict(X)
         err = np.linalg.norm(mean - Y, axis=1) / np.linalg.norm(Y, axis=1)
         best = 0.0
@@ -134,7 +146,7 @@ class Surrogate:
         mean, spread = self.predict(X)
         t_inf = time.perf_counter() - t0
         fb = np.nonzero(spread > self.threshold)[0]
-        out = mean.copy()
+        out = mean.astype(np.float64)
         t1 = time.perf_counter()
         if fb.size:
             _, Yfb = simulate([seeds[i] for i in fb], batch=batch, **sim_kw)
@@ -143,16 +155,60 @@ class Surrogate:
         return out, dict(fallback=fb, t_inference=t_inf, t_fallback=t_lb, spread=spread)
 
 
+def study(train: int = 4096, test: int = 512, val: int = 512, members: int = 4, epochs: int = 600,
+          batch: int = 256, lr: float = 2e-3, sim_batch: int = 1024, target: float = 0.02, data=None, log=None):
+    """Full surrogate study: `train` LB runs (seeds 3000 on; the last `val` held back to calibrate
+    the threshold), `test` held-out runs (seeds 9000 on) for the error and the speedup
+    T(batched LB of all held-out runs) / (T(ensemble inference) + T(batched LB of the fallback rows)).
+    `data`: optional dict with X, Y of the training runs (skips simulating them)."""
+    import torch
+
+    seeds = list(range(9000, 9000 + test))
+    Xt = features([wl.surrogate_inputs(x) for x in seeds])
+    t0 = time.perf_counter()
+    if data is not None:
+        X, Y = data["X"][:train], data["Y"][:train]
+    else:
+        inp, Y = simulate(range(3000, 3000 + train), batch=sim_batch, log=log)
+        X = features(inp)
+    t_data = time.perf_counter() - t0
+    ntr = train - val
+    s = Surrogate(members=members, max_batch=max(batch, test, val))
+    t_fit = s.fit(X[:ntr], Y[:ntr], epochs=epochs, batch=batch, lr=lr, log=log)
+    th = s.calibrate(X[ntr:], Y[ntr:], target=target)
+    if log:
+        log(f"surrogate: threshold {th:.4g} on the spread")
+
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, Yt = simulate(seeds, batch=test)
+    t_lb = time.perf_counter() - t1
+    s.predict(Xt)   # first call pays one-off costs
+    out, info = s.predict_with_fallback(seeds, Xt, batch=test)
+    mean, _ = s.predict(Xt)
+    err = np.linalg.norm(out - Yt, axis=1) / np.linalg.norm(Yt, axis=1)
+    err_nn = np.linalg.norm(mean - Yt, axis=1) / np.linalg.norm(Yt, axis=1)
+    t_sur = info["t_inference"] + info["t_fallback"]
+
+    def stats(e):
+        return dict(mean=round(float(e.mean()), 6), p95=round(float(np.quantile(e, 0.95)), 6),
+                    max=round(float(e.max()), 6), frac_le_target=float(np.mean(e <= target)))
+
+    return dict(
+        observable="centre-of-mass displacement along the pull, 64 samples", target_rel_l2=target,
+        train_runs=train, held_out_runs=test, members=members, widths=s.widths,
+        t_lb_data_s=round(t_data, 3), t_fit_s=round(t_fit, 3), threshold=round(th, 6),
+        t_lb_all_s=round(t_lb, 4), t_inference_s=round(info["t_inference"], 5),
+        t_fallback_s=round(info["t_fallback"], 4), n_fallback=int(info["fallback"].size),
+        speedup=round(t_lb / t_sur, 2), err_with_fallback=stats(err), err_network_only=stats(err_nn))
+
+
 def main(argv=None):
-    """Full surrogate study: 4096 LB runs for training (the last 512 held back to calibrate the
-    threshold), 512 held-out runs for the error and the speedup; prints one JSON line."""
     import argparse
     import json
     import sys
 
-    import torch
-
-    ap = argparse.ArgumentParser()
+    ap = argparse.ArgumentParser(description=study.__doc__)
     ap.add_argument("--train", type=int, default=4096)
     ap.add_argument("--test", type=int, default=512)
     ap.add_argument("--val", type=int, default=512)
@@ -163,44 +219,22 @@ def main(argv=None):
     ap.add_argument("--sim-batch", type=int, default=1024)
     ap.add_argument("--target", type=float, default=0.02)
     ap.add_argument("--out", default="")
+    ap.add_argument("--save-data", default="", help="only simulate; write both series of both sets to this .npz")
+    ap.add_argument("--load-data", default="", help="read the training series from this .npz")
     a = ap.parse_args(argv)
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
-    t0 = time.perf_counter()
-    inp, Y = simulate(range(3000, 3000 + a.train), batch=a.sim_batch, log=log)
-    t_data = time.perf_counter() - t0
-    X = features(inp)
-    ntr = a.train - a.val
-    s = Surrogate(members=a.members, max_batch=max(a.batch, a.test, a.val))
-    t_fit = s.fit(X[:ntr], Y[:ntr], epochs=a.epochs, batch=a.batch, lr=a.lr, log=log)
-    th = s.calibrate(X[ntr:], Y[ntr:], target=a.target)
-    log(f"surrogate: threshold {th:.4g} on the spread")
-
-    seeds = list(range(9000, 9000 + a.test))
-    Xt = features([wl.surrogate_inputs(x) for x in seeds])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    _, Yt = simulate(seeds, batch=a.test)
-    t_lb = time.perf_counter() - t1
-    s.predict(Xt)   # first call pays one-off costs
-    out, info = s.predict_with_fallback(seeds, Xt, batch=a.test)
-    mean, _ = s.predict(Xt)
-    err = np.linalg.norm(out - Yt, axis=1) / np.linalg.norm(Yt, axis=1)
-    err_nn = np.linalg.norm(mean - Yt, axis=1) / np.linalg.norm(Yt, axis=1)
-    t_sur = info["t_inference"] + info["t_fallback"]
-    res = dict(
-        train_runs=a.train, held_out_runs=a.test, members=a.members, widths=s.widths,
-        t_lb_data_s=round(t_data, 3), t_fit_s=round(t_fit, 3), threshold=th,
-        t_lb_all_s=round(t_lb, 4), t_inference_s=round(info["t_inference"], 5),
-        t_fallback_s=round(info["t_fallback"], 4), n_fallback=int(info["fallback"].size),
-        speedup=round(t_lb / t_sur, 2),
-        err_with_fallback=dict(mean=float(err.mean()), p95=float(np.quantile(err, 0.95)), max=float(err.max()),
-                               frac_le_target=float(np.mean(err <= a.target))),
-        err_network_only=dict(mean=float(err_nn.mean()), p95=float(np.quantile(err_nn, 0.95)),
-                              max=float(err_nn.max()), frac_le_target=float(np.mean(err_nn <= a.target))),
-    )
+    if a.save_data:
+        inp, Yb = simulate(range(3000, 3000 + a.train), batch=a.sim_batch, observable="both", log=log)
+        seeds = list(range(9000, 9000 + a.test))
+        _, Ytb = simulate(seeds, batch=a.test, observable="both")
+        np.savez(a.save_data, X=features(inp), Y=Yb["distance"], F=Yb["force"],
+                 Xt=features([wl.surrogate_inputs(x) for x in seeds]), Yt=Ytb["distance"], Ft=Ytb["force"])
+        return None
+    data = dict(np.load(a.load_data)) if a.load_data else None
+    res = study(a.train, a.test, a.val, a.members, a.epochs, a.batch, a.lr, a.sim_batch, a.target, data, log)
     line = json.dumps(res)
     print(line, flush=True)
     if a.out:
