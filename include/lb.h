@@ -134,7 +134,12 @@ int lb_read_fields(lb_handle *h, int32_t sim, uint32_t field_mask, double *host_
 int lb_body_force(lb_handle *h, int32_t sim, int32_t body, double out[8]);
 
 /* lb_body_force for every body of every simulation at once (simulations in order, bodies in
- * order within each): 8 doubles per body into host_out (capacity n_out doubles).  Synchronous. */
+ * order within each): 10 doubles per body into host_out (capacity n_out doubles, LB_ERANGE if
+ * smaller than 10 * total bodies): the 8 values of lb_body_force, then [8..9] the area-weighted
+ * restoring force, the sum over sites of (area of the site's unit cell [x-1/2, x+1/2] x
+ * [y-1/2, y+1/2] inside the node polygon) * div sigma^p, which unlike out[0..1] varies
+ * continuously as the body moves (the same integral over the body, Sec. 4 and Fig. 6, with a
+ * different quadrature).  Synchronous. */
 int lb_body_forces(lb_handle *h, double *host_out, size_t n_out);
 
 /* FP64 conservation sums of simulation `sim` at the current time (synchronous):

@@ -80,6 +80,10 @@ def lib():
         L.orc_observe.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, ctypes.POINTER(_Body),
                                   _dp, _dp, _dp, _dp, ctypes.c_int, _dp]
         L.orc_body_force.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Body), _dp, _dp]
+        L.orc_body_force_area.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Body), _dp, _dp]
+        L.orc_cell_area.argtypes = [ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double]
+        L.orc_cell_area.restype = ctypes.c_double
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_get_threads.restype = ctypes.c_int
         _lib = L
@@ -238,6 +242,13 @@ class Sim:
         lib().orc_body_force(ctypes.byref(self.p), ctypes.byref(bc), _ptr(self.sigma), _ptr(out))
         return out
 
+    def body_force_area(self, b: int) -> np.ndarray:
+        """Area-weighted restoring force of body b (see orc_body_force_area)."""
+        out = np.zeros(2)
+        bc = self.bodies[b].cstruct()
+        lib().orc_body_force_area(ctypes.byref(self.p), ctypes.byref(bc), _ptr(self.sigma), _ptr(out))
+        return out
+
     def spread(self, R: np.ndarray, f: np.ndarray):
         nx, ny = self.p.nx, self.p.ny
         R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1)
@@ -253,6 +264,12 @@ class Sim:
         out = np.zeros(R.size)
         lib().orc_interp(ctypes.byref(self.p), R.size // 2, _ptr(R), _ptr(ux), _ptr(uy), _ptr(out))
         return out.reshape(-1, 2)
+
+
+def cell_area(R: np.ndarray, x0: float, x1: float, y0: float, y1: float) -> float:
+    """Area of the polygon with nodes R (n, 2) inside the box [x0, x1] x [y0, y1]."""
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    return float(lib().orc_cell_area(R.shape[0], _ptr(R), x0, x1, y0, y1))
 
 
 def polygon(cx: float, cy: float, radius: float, n: int) -> np.ndarray:

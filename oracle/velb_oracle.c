@@ -623,3 +623,76 @@ void orc_body_force(const orc_params *p, const orc_body *b, const double *sigma,
     out[2] = cx / b->n;
     out[3] = cy / b->n;
 }
+
+/* ------------------------------------------------------------------------------------------ */
+/* area-weighted restoring force                                                               */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Clip a polygon against one half-plane (Sutherland-Hodgman): keep points with
+ * side * (coordinate axis of q - c) >= 0.  Returns the new vertex count. */
+static int clip_half(const double *in, int n, double *out, int axis, double c, double side) {
+    int m = 0;
+    for (int i = 0; i < n; ++i) {
+        const double *a = in + 2 * ((i + n - 1) % n), *b = in + 2 * i;
+        double da = side * (a[axis] - c), db = side * (b[axis] - c);
+        if (db >= 0.0) {
+            if (da < 0.0) {
+                double t = da / (da - db);
+                out[2 * m] = a[0] + t * (b[0] - a[0]);
+                out[2 * m + 1] = a[1] + t * (b[1] - a[1]);
+                out[2 * m + axis] = c;
+                ++m;
+            }
+            out[2 * m] = b[0];
+            out[2 * m + 1] = b[1];
+            ++m;
+        } else if (da >= 0.0) {
+            double t = da / (da - db);
+            out[2 * m] = a[0] + t * (b[0] - a[0]);
+            out[2 * m + 1] = a[1] + t * (b[1] - a[1]);
+            out[2 * m + axis] = c;
+            ++m;
+        }
+    }
+    return m;
+}
+
+static double shoelace(const double *q, int n) {
+    double a = 0.0;
+    for (int i = 0, j = n - 1; i < n; j = i++) a += q[2 * j] * q[2 * i + 1] - q[2 * i] * q[2 * j + 1];
+    return 0.5 * a;
+}
+
+double orc_cell_area(int n, const double *R, double x0, double x1, double y0, double y1) {
+    double *A = malloc(sizeof(double) * 2 * (n + 8)), *B = malloc(sizeof(double) * 2 * (n + 8));
+    int m = n;
+    memcpy(A, R, sizeof(double) * 2 * n);
+    m = clip_half(A, m, B, 0, x0, 1.0);
+    m = clip_half(B, m, A, 0, x1, -1.0);
+    m = clip_half(A, m, B, 1, y0, 1.0);
+    m = clip_half(B, m, A, 1, y1, -1.0);
+    double area = m >= 3 ? shoelace(A, m) : 0.0;
+    free(A);
+    free(B);
+    return shoelace(R, n) < 0.0 ? -area : area;
+}
+
+void orc_body_force_area(const orc_params *p, const orc_body *b, const double *sigma, double *out) {
+    const size_t N = (size_t)p->nx * p->ny;
+    const double *sxx = sigma, *syy = sigma + N, *sxy = sigma + 2 * N;
+    double minx = b->R[0], maxx = b->R[0], miny = b->R[1], maxy = b->R[1];
+    for (int a = 0; a < b->n; ++a) {
+        minx = fmin(minx, b->R[2 * a]); maxx = fmax(maxx, b->R[2 * a]);
+        miny = fmin(miny, b->R[2 * a + 1]); maxy = fmax(maxy, b->R[2 * a + 1]);
+    }
+    double fx = 0.0, fy = 0.0;
+    for (int y = (int)floor(miny + 0.5); y <= (int)ceil(maxy - 0.5); ++y)
+        for (int x = (int)floor(minx + 0.5); x <= (int)ceil(maxx - 0.5); ++x) {
+            double w = orc_cell_area(b->n, b->R, x - 0.5, x + 0.5, y - 0.5, y + 0.5);
+            if (w == 0.0) continue;
+            fx += w * (ddx(p, sxx, x, y, GHOST_EVEN) + ddy(p, sxy, x, y, GHOST_EVEN));
+            fy += w * (ddx(p, sxy, x, y, GHOST_EVEN) + ddy(p, syy, x, y, GHOST_EVEN));
+        }
+    out[0] = fx;
+    out[1] = fy;
+}

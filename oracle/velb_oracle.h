@@ -87,6 +87,17 @@ void orc_observe(const orc_params *p, int n_bodies, const orc_body *bodies,
  * node polygon (even-odd rule), in out[0..1]; out[2..3] = centre of mass of the nodes */
 void orc_body_force(const orc_params *p, const orc_body *b, const double *sigma, double *out);
 
+/* area of (node polygon) intersected with the box [x0, x1] x [y0, y1], by clipping the polygon
+ * against the box's four half-planes and taking the shoelace area; positive for either
+ * orientation of a simple polygon */
+double orc_cell_area(int n, const double *R, double x0, double x1, double y0, double y1);
+
+/* area-weighted restoring force: the integral of div(sigma) over the body with div(sigma) taken
+ * constant on each lattice cell [x-1/2, x+1/2] x [y-1/2, y+1/2], i.e. the sum over sites of
+ * (cell area inside the polygon) * div(sigma); out[0..1].  Unlike the site sum above it varies
+ * continuously with the node positions. */
+void orc_body_force_area(const orc_params *p, const orc_body *b, const double *sigma, double *out);
+
 #ifdef __cplusplus
 }
 #endif

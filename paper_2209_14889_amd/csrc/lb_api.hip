@@ -323,7 +323,7 @@ Plan make_plan(const lb_sim_params *sims, int n_sims, const Opt &o) {
     pl.max_partial = 1024;
     pl.oPartial = a.take(sizeof(double) * 3 * pl.max_partial);
     pl.oOut = a.take(sizeof(double) * 16);
-    pl.oOutAll = a.take(sizeof(double) * 6 * std::max(1, total_bodies));
+    pl.oOutAll = a.take(sizeof(double) * kBodyOut * std::max(1, total_bodies));
     pl.oStage = a.take(10 * maxN * 4);
     pl.bytes = a.off + 256;
     return pl;
@@ -997,6 +997,9 @@ static void body_out(const lb_handle *h, const BodyDev &B, const double *r, doub
     out[7] = r[5];
 }
 
+// the batched layout adds the area-weighted restoring force after the 8 values above
+constexpr int kBodiesOut = 10;
+
 int lb_body_force(lb_handle *h, int32_t sim, int32_t body, double out[8]) {
     if (!h || !out) return fail(LB_EINVAL, "NULL argument");
     if (sim < 0 || sim >= h->n_sims) return fail(LB_ERANGE, "sim index out of range");
@@ -1005,7 +1008,7 @@ int lb_body_force(lb_handle *h, int32_t sim, int32_t body, double out[8]) {
     if (rc) return rc;
     const int bi = h->hs[sim].b0 + body;
     HIPCHK(launch_body_force(h->stream, h->d_sims, h->d_bodies, bi, 1, h->cur, h->d_out_all));
-    double r[6];
+    double r[kBodyOut];
     HIPCHK(hipMemcpyAsync(r, h->d_out_all, sizeof r, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     body_out(h, h->hb[bi], r, out);
@@ -1015,15 +1018,20 @@ int lb_body_force(lb_handle *h, int32_t sim, int32_t body, double out[8]) {
 int lb_body_forces(lb_handle *h, double *out, size_t n_out) {
     if (!h || !out) return fail(LB_EINVAL, "NULL argument");
     const size_t nb = h->hb.size();
-    if (n_out < 8 * nb) return fail(LB_ERANGE, "output buffer too small");
+    if (n_out < (size_t)kBodiesOut * nb) return fail(LB_ERANGE, "output buffer too small");
     if (nb == 0) return LB_OK;
     int rc = check_status(h);
     if (rc) return rc;
     HIPCHK(launch_body_force(h->stream, h->d_sims, h->d_bodies, 0, (int)nb, h->cur, h->d_out_all));
-    std::vector<double> r(6 * nb);
-    HIPCHK(hipMemcpyAsync(r.data(), h->d_out_all, sizeof(double) * 6 * nb, hipMemcpyDeviceToHost, h->stream));
+    std::vector<double> r(kBodyOut * nb);
+    HIPCHK(hipMemcpyAsync(r.data(), h->d_out_all, sizeof(double) * kBodyOut * nb, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
-    for (size_t b = 0; b < nb; ++b) body_out(h, h->hb[b], r.data() + 6 * b, out + 8 * b);
+    for (size_t b = 0; b < nb; ++b) {
+        double *o = out + kBodiesOut * b;
+        body_out(h, h->hb[b], r.data() + kBodyOut * b, o);
+        o[8] = r[kBodyOut * b + 6];
+        o[9] = r[kBodyOut * b + 7];
+    }
     return check_status(h);
 }
 

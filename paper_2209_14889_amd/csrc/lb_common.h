@@ -8,6 +8,7 @@ namespace lbk {
 constexpr int kMaxNodes = 1024;     // nodes per body
 constexpr int kMaxBodies = 64;      // bodies per simulation
 constexpr int kPatchTile = 16;      // immersed-boundary gather block: 16 x 16 patch sites
+constexpr int kBodyOut = 8;         // doubles per body written by the observable kernel
 constexpr int kMaxCand = 512;       // nodes whose footprint can reach one gather block
 constexpr int kTab = 4096;          // stiffness-table intervals over s = |P|^2 in [0, P_clamp^2]
 constexpr int kHalo = 4;            // fused kernel: polarization halo depth (stress and h use 3)

@@ -811,21 +811,49 @@ __global__ __launch_bounds__(64) void k_sums_final(const SimDev *__restrict__ si
     }
 }
 
-// body observables: restoring force (sum of div sigma over sites inside the node polygon),
-// centre of mass, total node force; one 256-thread block
+// Integral along the directed edge (xa, ya) -> (xb, yb), restricted to y0 <= y <= y1, of
+// g(x) dy with g(x) = clamp(x, x0, x1) - x0.  Summed over a closed polygon this is, by Green's
+// theorem, the signed area of the polygon inside the box [x0, x1] x [y0, y1].  g is piecewise
+// linear along the edge, so the midpoint rule on the pieces between its kinks is exact.
+__device__ __forceinline__ double edge_box(double xa, double ya, double xb, double yb, double x0, double x1,
+                                           double y0, double y1) {
+    const double lo = fmax(fmin(ya, yb), y0), hi = fmin(fmax(ya, yb), y1);
+    if (!(hi > lo)) return 0.0;   // outside the band, or a horizontal edge
+    const double s = (xb - xa) / (yb - ya);
+    const double xl = xa + s * (lo - ya), xh = xa + s * (hi - ya);
+    double ta = 0.0, tb = 0.0;
+    if (xh != xl) {
+        const double inv = 1.0 / (xh - xl);
+        ta = fmin(fmax((x0 - xl) * inv, 0.0), 1.0);
+        tb = fmin(fmax((x1 - xl) * inv, 0.0), 1.0);
+        if (ta > tb) {
+            const double u = ta;
+            ta = tb;
+            tb = u;
+        }
+    }
+    auto g = [&](double t) { return fmin(fmax(xl + t * (xh - xl), x0), x1) - x0; };
+    const double integral = ta * g(0.5 * ta) + (tb - ta) * g(0.5 * (ta + tb)) + (1.0 - tb) * g(0.5 * (tb + 1.0));
+    return (yb > ya ? 1.0 : -1.0) * (hi - lo) * integral;
+}
+
+// body observables, one 256-thread block per body: restoring force as the sum of div sigma over
+// the sites inside the node polygon (even-odd rule), centre of mass, total node force, and the
+// area-weighted restoring force: the sum over sites of (area of the site's unit cell inside the
+// polygon) * div sigma, which varies continuously with the node positions
 __global__ __launch_bounds__(256) void k_body_force(const SimDev *__restrict__ sims, const BodyDev *__restrict__ bodies,
                                                     int body0, int cur, double *__restrict__ out_all) {
     __shared__ double2 sR[kMaxNodes];
-    __shared__ double sh[8][4];
+    __shared__ double sh[9][4];
     const BodyDev &B = bodies[body0 + blockIdx.x];
-    double *out = out_all + 6 * blockIdx.x;
+    double *out = out_all + kBodyOut * blockIdx.x;
     const SimDev &S = sims[B.sim];
     const int n = B.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const double2 *R = reinterpret_cast<const double2 *>(B.R[cur]);
     const double2 *Fn = reinterpret_cast<const double2 *>(B.fnode);
-    double mnx = 1e300, mny = 1e300, mxx = -1e300, mxy = -1e300, cx = 0, cy = 0, fx = 0, fy = 0;
+    double mnx = 1e300, mny = 1e300, mxx = -1e300, mxy = -1e300, cx = 0, cy = 0, fx = 0, fy = 0, ar = 0;
     for (int a = tid; a < n; a += 256) {
-        double2 r = R[a];
+        double2 r = R[a], q = R[a == 0 ? n - 1 : a - 1];
         sR[a] = r;
         mnx = fmin(mnx, r.x);
         mny = fmin(mny, r.y);
@@ -835,11 +863,12 @@ __global__ __launch_bounds__(256) void k_body_force(const SimDev *__restrict__ s
         cy += r.y;
         fx += Fn[a].x;
         fy += Fn[a].y;
+        ar += q.x * r.y - r.x * q.y;
     }
-    double v8[8] = {wave_min(mnx), wave_min(mny), wave_max(mxx), wave_max(mxy),
-                    wave_sum(cx), wave_sum(cy), wave_sum(fx), wave_sum(fy)};
+    double v9[9] = {wave_min(mnx), wave_min(mny), wave_max(mxx), wave_max(mxy),
+                    wave_sum(cx),  wave_sum(cy),  wave_sum(fx),  wave_sum(fy), wave_sum(ar)};
     if (lane == 0)
-        for (int k = 0; k < 8; ++k) sh[k][wv] = v8[k];
+        for (int k = 0; k < 9; ++k) sh[k][wv] = v9[k];
     __syncthreads();
     mnx = fmin(fmin(sh[0][0], sh[0][1]), fmin(sh[0][2], sh[0][3]));
     mny = fmin(fmin(sh[1][0], sh[1][1]), fmin(sh[1][2], sh[1][3]));
@@ -849,30 +878,55 @@ __global__ __launch_bounds__(256) void k_body_force(const SimDev *__restrict__ s
     double scy = (sh[5][0] + sh[5][1]) + (sh[5][2] + sh[5][3]);
     double sfx = (sh[6][0] + sh[6][1]) + (sh[6][2] + sh[6][3]);
     double sfy = (sh[7][0] + sh[7][1]) + (sh[7][2] + sh[7][3]);
+    const double orient = (sh[8][0] + sh[8][1]) + (sh[8][2] + sh[8][3]) < 0.0 ? -1.0 : 1.0;
     __syncthreads();
-    const int x0 = (int)ceil(mnx), x1 = (int)floor(mxx), y0 = (int)ceil(mny), y1 = (int)floor(mxy);
-    const int wdt = x1 - x0 + 1, hgt = y1 - y0 + 1;
     const size_t N = (size_t)S.nx * S.ny;
     const float *sg = S.sig[cur];
+    auto divx = [&](const Nb &q) {
+        return 0.5 * ((double)sg[q.e] - (double)sg[q.w]) + 0.5 * ((double)sg[2 * N + q.n] - (double)sg[2 * N + q.s]);
+    };
+    auto divy = [&](const Nb &q) {
+        return 0.5 * ((double)sg[2 * N + q.e] - (double)sg[2 * N + q.w]) + 0.5 * ((double)sg[N + q.n] - (double)sg[N + q.s]);
+    };
+    // sites strictly inside (even-odd)
     double ax = 0.0, ay = 0.0;
-    for (int i = tid; i < wdt * hgt; i += 256) {
-        const int X = x0 + i % wdt, Y = y0 + i / wdt;
-        bool in = false;
-        for (int a = 0, b = n - 1; a < n; b = a++) {
-            double xa = sR[a].x, ya = sR[a].y, xb = sR[b].x, yb = sR[b].y;
-            if ((ya > Y) != (yb > Y) && X < (xb - xa) * (Y - ya) / (yb - ya) + xa) in = !in;
+    {
+        const int x0 = (int)ceil(mnx), x1 = (int)floor(mxx), y0 = (int)ceil(mny), y1 = (int)floor(mxy);
+        const int wdt = x1 - x0 + 1, hgt = y1 - y0 + 1;
+        for (int i = tid; i < wdt * hgt; i += 256) {
+            const int X = x0 + i % wdt, Y = y0 + i / wdt;
+            bool in = false;
+            for (int a = 0, b = n - 1; a < n; b = a++) {
+                double xa = sR[a].x, ya = sR[a].y, xb = sR[b].x, yb = sR[b].y;
+                if ((ya > Y) != (yb > Y) && X < (xb - xa) * (Y - ya) / (yb - ya) + xa) in = !in;
+            }
+            if (!in) continue;
+            Nb q = nbrs(wrapi(X, S.nx), wrapi(Y, S.ny), S.nx, S.ny);
+            ax += divx(q);
+            ay += divy(q);
         }
-        if (!in) continue;
-        Nb q = nbrs(wrapi(X, S.nx), wrapi(Y, S.ny), S.nx, S.ny);
-        ax += 0.5 * ((double)sg[q.e] - (double)sg[q.w]) + 0.5 * ((double)sg[2 * N + q.n] - (double)sg[2 * N + q.s]);
-        ay += 0.5 * ((double)sg[2 * N + q.e] - (double)sg[2 * N + q.w]) + 0.5 * ((double)sg[N + q.n] - (double)sg[N + q.s]);
     }
-    ax = wave_sum(ax);
-    ay = wave_sum(ay);
-    if (lane == 0) {
-        sh[0][wv] = ax;
-        sh[1][wv] = ay;
+    // every cell [X - 1/2, X + 1/2] x [Y - 1/2, Y + 1/2] the bounding box touches, weighted by area
+    double bx = 0.0, by = 0.0;
+    {
+        const int x0 = (int)floor(mnx + 0.5), x1 = (int)ceil(mxx - 0.5), y0 = (int)floor(mny + 0.5),
+                  y1 = (int)ceil(mxy - 0.5);
+        const int wdt = x1 - x0 + 1, hgt = y1 - y0 + 1;
+        for (int i = tid; i < wdt * hgt; i += 256) {
+            const int X = x0 + i % wdt, Y = y0 + i / wdt;
+            double w = 0.0;
+            for (int a = 0, b = n - 1; a < n; b = a++)
+                w += edge_box(sR[b].x, sR[b].y, sR[a].x, sR[a].y, X - 0.5, X + 0.5, Y - 0.5, Y + 0.5);
+            w *= orient;
+            if (w == 0.0) continue;
+            Nb q = nbrs(wrapi(X, S.nx), wrapi(Y, S.ny), S.nx, S.ny);
+            bx += w * divx(q);
+            by += w * divy(q);
+        }
     }
+    double red[4] = {wave_sum(ax), wave_sum(ay), wave_sum(bx), wave_sum(by)};
+    if (lane == 0)
+        for (int k = 0; k < 4; ++k) sh[k][wv] = red[k];
     __syncthreads();
     if (tid == 0) {
         out[0] = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
@@ -881,6 +935,8 @@ __global__ __launch_bounds__(256) void k_body_force(const SimDev *__restrict__ s
         out[3] = scy / n;
         out[4] = sfx;
         out[5] = sfy;
+        out[6] = (sh[2][0] + sh[2][1]) + (sh[2][2] + sh[2][3]);
+        out[7] = (sh[3][0] + sh[3][1]) + (sh[3][2] + sh[3][3]);
     }
 }
 

@@ -238,11 +238,12 @@ class Sim:
         return dict(restoring=out[0:2].copy(), pull=out[2:4].copy(), com=out[4:6].copy(), node_force=out[6:8].copy())
 
     def body_forces(self) -> np.ndarray:
-        """(total bodies, 8): restoring force (2), pull (2), centre of mass (2), node force (2)."""
+        """(total bodies, 10): restoring force as the inside-site sum (2), pull (2), centre of
+        mass (2), node force (2), area-weighted restoring force (2)."""
         nb = sum(len(s.bodies) for s in self.specs)
-        out = np.empty(8 * max(1, nb))
+        out = np.empty(10 * max(1, nb))
         check(lib().lb_body_forces(self.h, out.ctypes.data_as(_dp), out.size))
-        return out[:8 * nb].reshape(nb, 8).copy()
+        return out[:10 * nb].reshape(nb, 10).copy()
 
     def conservation(self, sim: int = 0) -> np.ndarray:
         out = np.empty(3)

@@ -2,11 +2,13 @@
 fallback and as judge of its error.
 
 Inputs (5): stress diffusion D_p, relaxation time, body radius, director angle to the pull, and
-polarization magnitude P_eq (alpha = -P_eq^2).  Output: the distance trajectory of the body (its
-centre-of-mass displacement along the pull, the quantity of Fig. 5) sampled every 64 steps of a 4096-step pull-and-release run on a 128 x 128 lattice
-(64 samples).  The restoring force along the pull (the sum of div sigma^p over the sites inside the
-body) is recorded too, but it jumps whenever a site crosses the body outline, which no smooth map of
-the five inputs can follow to a few per cent; the displacement integrates it and is smooth.
+polarization magnitude P_eq (alpha = -P_eq^2).  Output: the viscoelastic restoring force on the
+body along the pull (the integral of div sigma^p over the body, Sec. 4 and Fig. 6) sampled every
+64 steps of a 4096-step pull-and-release run on a 128 x 128 lattice (64 samples).  The integral is
+taken with area weights (each site's div sigma^p times the area of its unit cell inside the node
+polygon): the plain sum over the sites inside jumps by whole sites as the outline moves across the
+lattice, by around 10 per cent between radii 0.1 apart, which no smooth map of the five inputs can
+follow to a few per cent; the area-weighted form varies continuously.
 
 Training data comes from batched LB ensembles run by the library; the networks (an ensemble of M
 members with different seeds) are trained by the library's own forward/backward/Adam kernels.  The
@@ -40,35 +42,37 @@ def features(inputs) -> np.ndarray:
     return (2.0 * np.asarray(x, dtype=np.float64) - 1.0).astype(np.float32)
 
 
+OBSERVABLES = ("force", "force_sites", "distance")
+
+
 def simulate(seeds, batch: int = 512, n: int = wl.C5_N, steps: int = wl.C5_STEPS,
-             every: int = wl.C5_SAMPLE_EVERY, observable: str = "distance", log=None):
+             every: int = wl.C5_SAMPLE_EVERY, observable: str = "force", log=None):
     """Run the LB method for the given seeds in batched ensembles; returns (inputs, series) with
-    series[i, k] the observable after (k+1)*every steps: "distance" (centre-of-mass displacement
-    along +x), "force" (restoring force along +x), or "both" (a dict of the two)."""
+    series[i, k] the observable after (k+1)*every steps: "force" (area-weighted restoring force
+    along the pull, +x), "force_sites" (the inside-site sum along +x), "distance" (centre-of-mass
+    displacement along +x), or "all" (a dict of the three)."""
     seeds = list(seeds)
-    inputs, dist, force = [], [], []
+    inputs, series = [], {k: [] for k in OBSERVABLES}
     for c0 in range(0, len(seeds), batch):
         chunk = seeds[c0:c0 + batch]
         specs = [wl.surrogate_member(s, n) for s in chunk]
         sim = lb.Sim(specs, lb.make_options(graph_chunk=every if every % 2 == 0 else 0))
         x0 = sim.body_forces()[:, 4]
-        D = np.empty((len(chunk), steps // every))
-        F = np.empty_like(D)
+        cur = {k: np.empty((len(chunk), steps // every)) for k in OBSERVABLES}
         for k in range(steps // every):
             sim.step(every)
             bf = sim.body_forces()
-            D[:, k] = bf[:, 4] - x0
-            F[:, k] = bf[:, 0]
+            cur["force"][:, k] = bf[:, 8]
+            cur["force_sites"][:, k] = bf[:, 0]
+            cur["distance"][:, k] = bf[:, 4] - x0
         sim.close()
         inputs += [s.meta for s in specs]
-        dist.append(D)
-        force.append(F)
+        for k in OBSERVABLES:
+            series[k].append(cur[k])
         if log:
             log(f"surrogate: simulated {c0 + len(chunk)}/{len(seeds)} runs")
-    D, F = np.concatenate(dist), np.concatenate(force)
-    if observable == "both":
-        return inputs, dict(distance=D, force=F)
-    return inputs, (D if observable == "distance" else F)
+    out = {k: np.concatenate(v) for k, v in series.items()}
+    return inputs, (out if observable == "all" else out[observable])
 
 
 class Surrogate:
@@ -87,32 +91,38 @@ class Surrogate:
     def _t(self, a):
         return self.torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=self.device)
 
-    def fit(self, X, Y, epochs: int = 1500, batch: int = 512, lr: float = 2e-3, lr_min: float = 2e-5,
+    def fit(self, X, Y, epochs: int = 1800, batch: int = 256, lr: float = 2e-3, lr_min: float = 2e-5,
             seed: int = 0, log=None):
-        """Adam with cosine learning-rate decay on the mean squared relative error of each series."""
+        """Adam with cosine learning-rate decay on the mean squared relative error of each series.
+        The members train concurrently, each on its own stream and its own shuffling of the data."""
+        torch = self.torch
         self.scale = float(np.sqrt(np.mean(np.asarray(Y) ** 2)))
         Xt, Yt = self._t(X), self._t(np.asarray(Y) / self.scale)
         n = Xt.shape[0]
-        rng = np.random.default_rng(seed)
+        rngs = [np.random.default_rng(seed + 7919 * m) for m in range(len(self.nets))]
         steps_per_epoch = max(1, n // batch)
         total = epochs * steps_per_epoch
-        loss = self.torch.zeros(1, dtype=self.torch.float32, device=self.device)
-        self.torch.cuda.synchronize()
+        losses = [torch.zeros(1, dtype=torch.float32, device=self.device) for _ in self.nets]
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for m, net in enumerate(self.nets):
-            step = 0
-            for ep in range(epochs):
-                perm = self.torch.as_tensor(rng.permutation(n)[:steps_per_epoch * batch], device=self.device)
-                Xe, Ye = Xt[perm].contiguous(), Yt[perm].contiguous()
-                self.torch.cuda.synchronize()
-                for b in range(steps_per_epoch):
-                    lr_t = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * step / total))
+        step = 0
+        for ep in range(epochs):
+            shuffled = []
+            for r in rngs:
+                perm = torch.as_tensor(r.permutation(n)[:steps_per_epoch * batch], device=self.device)
+                shuffled.append((Xt[perm].contiguous(), Yt[perm].contiguous()))
+            torch.cuda.synchronize()   # the shuffled copies are complete before the networks' streams read them
+            for b in range(steps_per_epoch):
+                lr_t = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * step / total))
+                for net, (Xe, Ye), loss in zip(self.nets, shuffled, losses):
                     net.train_step(Xe[b * batch:(b + 1) * batch], Ye[b * batch:(b + 1) * batch], lr_t, loss)
-                    step += 1
-                net.stream.synchronize()
-                if log and (ep + 1) % max(1, epochs // 5) == 0:
-                    log(f"surrogate: member {m} epoch {ep + 1}/{epochs} batch loss {float(loss.item()):.3e}")
-        self.torch.cuda.synchronize()
+                step += 1
+            for net in self.nets:
+                net.stream.synchronize()   # before the shuffled copies are released
+            if log and (ep + 1) % max(1, epochs // 6) == 0:
+                log(f"surrogate: epoch {ep + 1}/{epochs} batch losses " +
+                    " ".join(f"{float(l.item()):.3e}" for l in losses))
+        torch.cuda.synchronize()
         return time.perf_counter() - t0
 
     def predict(self, X):
@@ -155,7 +165,7 @@ class Surrogate:
         return out, dict(fallback=fb, t_inference=t_inf, t_fallback=t_lb, spread=spread)
 
 
-def study(train: int = 4096, test: int = 512, val: int = 512, members: int = 4, epochs: int = 600,
+def study(train: int = 4096, test: int = 512, val: int = 512, members: int = 4, epochs: int = 1800,
           batch: int = 256, lr: float = 2e-3, sim_batch: int = 1024, target: float = 0.02, data=None, log=None):
     """Full surrogate study: `train` LB runs (seeds 3000 on; the last `val` held back to calibrate
     the threshold), `test` held-out runs (seeds 9000 on) for the error and the speedup
@@ -195,7 +205,7 @@ def study(train: int = 4096, test: int = 512, val: int = 512, members: int = 4, 
                     max=round(float(e.max()), 6), frac_le_target=float(np.mean(e <= target)))
 
     return dict(
-        observable="centre-of-mass displacement along the pull, 64 samples", target_rel_l2=target,
+        observable="area-weighted restoring force along the pull, 64 samples", target_rel_l2=target,
         train_runs=train, held_out_runs=test, members=members, widths=s.widths,
         t_lb_data_s=round(t_data, 3), t_fit_s=round(t_fit, 3), threshold=round(th, 6),
         t_lb_all_s=round(t_lb, 4), t_inference_s=round(info["t_inference"], 5),
@@ -213,13 +223,13 @@ def main(argv=None):
     ap.add_argument("--test", type=int, default=512)
     ap.add_argument("--val", type=int, default=512)
     ap.add_argument("--members", type=int, default=4)
-    ap.add_argument("--epochs", type=int, default=600)
+    ap.add_argument("--epochs", type=int, default=1800)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--sim-batch", type=int, default=1024)
     ap.add_argument("--target", type=float, default=0.02)
     ap.add_argument("--out", default="")
-    ap.add_argument("--save-data", default="", help="only simulate; write both series of both sets to this .npz")
+    ap.add_argument("--save-data", default="", help="only simulate; write every observable of both sets to this .npz")
     ap.add_argument("--load-data", default="", help="read the training series from this .npz")
     a = ap.parse_args(argv)
 
@@ -227,11 +237,12 @@ def main(argv=None):
         print(msg, file=sys.stderr, flush=True)
 
     if a.save_data:
-        inp, Yb = simulate(range(3000, 3000 + a.train), batch=a.sim_batch, observable="both", log=log)
+        inp, Yb = simulate(range(3000, 3000 + a.train), batch=a.sim_batch, observable="all", log=log)
         seeds = list(range(9000, 9000 + a.test))
-        _, Ytb = simulate(seeds, batch=a.test, observable="both")
-        np.savez(a.save_data, X=features(inp), Y=Yb["distance"], F=Yb["force"],
-                 Xt=features([wl.surrogate_inputs(x) for x in seeds]), Yt=Ytb["distance"], Ft=Ytb["force"])
+        _, Ytb = simulate(seeds, batch=a.test, observable="all")
+        np.savez(a.save_data, X=features(inp), Y=Yb["force"], Yt=Ytb["force"],
+                 Xt=features([wl.surrogate_inputs(x) for x in seeds]),
+                 **{f"{k}_train": Yb[k] for k in OBSERVABLES}, **{f"{k}_test": Ytb[k] for k in OBSERVABLES})
         return None
     data = dict(np.load(a.load_data)) if a.load_data else None
     res = study(a.train, a.test, a.val, a.members, a.epochs, a.batch, a.lr, a.sim_batch, a.target, data, log)

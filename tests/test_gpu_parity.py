@@ -80,6 +80,37 @@ def test_parity_c1_1000_steps():
     say("  restoring force gpu", bf_g["restoring"], "oracle", bf_r[:2])
     assert np.max(np.abs(bf_g["restoring"] - bf_r[:2])) <= 1e-4 * np.max(np.abs(bf_r[:2])) + 1e-12
     assert np.max(np.abs(bf_g["com"] - bf_r[2:])) <= 1e-5
+    area_g = g.body_forces()[0, 8:10]
+    area_r = r.body_force_area(0)
+    say("  area-weighted restoring force gpu", area_g, "oracle", area_r)
+    assert np.max(np.abs(area_g - area_r)) <= 1e-4 * np.max(np.abs(area_r)) + 1e-12
+
+
+def test_area_weighted_force_of_uniform_divergence():
+    """At t = 0 with sigma_xx = a x and sigma_xy = b y near the bodies, div sigma = (a + b, 0) at every
+    site they touch, so the area-weighted force is (a + b) times the polygon area exactly (the
+    polygon here is regular: area = n R^2 sin(2 pi / n) / 2)."""
+    w = wl.small_case(44, 96, 90, n_bodies=2, radius=7.3)
+    s0 = w.sims[0]
+    a, b = 3e-4, -1e-4
+    sig = np.zeros((3, s0.ny, s0.nx))
+    sig[0] = a * np.arange(s0.nx)[None, :]
+    sig[2] = b * np.arange(s0.ny)[:, None]
+    s0.sigma0 = sig.astype(np.float32).astype(np.float64)
+    for body in s0.bodies:   # keep every body away from the periodic seams of the ramps
+        assert 10 < body.R[:, 0].min() and body.R[:, 0].max() < s0.nx - 10
+        assert 10 < body.R[:, 1].min() and body.R[:, 1].max() < s0.ny - 10
+    say("case area-force uniform divergence 96x90 seed=44")
+    g = lb.Sim(w)
+    out = g.body_forces()
+    for k, body in enumerate(s0.bodies):
+        n = body.R.shape[0]
+        rad = float(np.hypot(*(body.R[0] - body.R.mean(axis=0))))
+        area = 0.5 * n * rad * rad * math.sin(2 * math.pi / n)
+        say(f"  body {k}: area {area:.6f} force {out[k, 8:10]}")
+        # FP32 stress values of size a * nx: differences carry ~1e-7 relative rounding
+        assert abs(out[k, 8] - (a + b) * area) <= 2e-6 * abs(a * s0.nx) * area
+        assert abs(out[k, 9]) <= 2e-6 * abs(a * s0.nx) * area
 
 
 def test_fused_and_multipass_agree():

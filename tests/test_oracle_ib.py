@@ -115,3 +115,84 @@ def test_pull_schedule_logistic():
     assert b.pull_factor(0) < 0.02 and b.pull_factor(1000) > 0.999 and b.pull_factor(4000) < 1e-20
     b2 = oracle.Body(R=oracle.polygon(0, 0, 3, 8), pull=(1.0, 0.0))
     assert b2.pull_factor(12345) == 1.0
+
+
+# --- area-weighted restoring force -------------------------------------------------------------
+
+def _star(seed, n=37, R=5.0, c=(20.3, 17.6)):
+    rng = np.random.default_rng(seed)
+    a = 2 * math.pi * np.arange(n) / n
+    r = R * (1 + 0.15 * np.sin(3 * a + rng.uniform(0, 6)) + 0.05 * rng.standard_normal(n))
+    return np.stack([c[0] + r * np.cos(a), c[1] + r * np.sin(a)], axis=1)
+
+
+def test_cell_area_of_an_axis_aligned_rectangle():
+    rect = np.array([[0.3, 0.2], [1.7, 0.2], [1.7, 1.1], [0.3, 1.1]])
+    expect = {(0, 0): 0.2 * 0.3, (1, 0): 1.0 * 0.3, (2, 0): 0.2 * 0.3,
+              (0, 1): 0.2 * 0.6, (1, 1): 1.0 * 0.6, (2, 1): 0.2 * 0.6}
+    for X in range(-1, 4):
+        for Y in range(-1, 3):
+            got = oracle.cell_area(rect, X - 0.5, X + 0.5, Y - 0.5, Y + 0.5)
+            assert abs(got - expect.get((X, Y), 0.0)) < 1e-15, (X, Y)
+    # either orientation
+    assert abs(oracle.cell_area(rect[::-1], 0.5, 1.5, 0.5, 1.5) - 0.6) < 1e-15
+
+
+def test_cell_areas_tile_the_regular_polygon():
+    for n, R in ((40, 6.0), (25, 4.3), (151, 24.0)):
+        P = oracle.polygon(31.37, 29.81, R, n)
+        tot = sum(oracle.cell_area(P, X - 0.5, X + 0.5, Y - 0.5, Y + 0.5)
+                  for X in range(int(31.37 - R) - 2, int(31.37 + R) + 3)
+                  for Y in range(int(29.81 - R) - 2, int(29.81 + R) + 3))
+        assert abs(tot - 0.5 * n * R * R * math.sin(2 * math.pi / n)) < 1e-11
+
+
+def test_cell_area_brute_force_point_count():
+    # fraction of a 300 x 300 grid of cell points inside the polygon (even-odd rule in numpy)
+    P = _star(3)
+    g = (np.arange(300) + 0.5) / 300 - 0.5
+    for X, Y in ((20, 22), (24, 17), (16, 14), (20, 17)):
+        px, py = np.meshgrid(X + g, Y + g)
+        inside = np.zeros(px.shape, bool)
+        for i in range(len(P)):
+            (xa, ya), (xb, yb) = P[i - 1], P[i]
+            cross = (ya > py) != (yb > py)
+            xint = xa + (xb - xa) * (py - ya) / np.where(yb == ya, 1.0, yb - ya)
+            inside ^= cross & (px < xint)
+        assert abs(oracle.cell_area(P, X - 0.5, X + 0.5, Y - 0.5, Y + 0.5) - inside.mean()) < 4e-3
+
+
+def _linear_sigma(nx, ny, a, b):
+    # sigma_xx = a x, sigma_xy = b y: div sigma = (a + b, 0) by central differences away from the
+    # periodic seams
+    s = np.zeros((3, ny, nx))
+    s[0] = a * np.arange(nx)[None, :]
+    s[2] = b * np.arange(ny)[:, None]
+    return s
+
+
+def test_area_force_of_a_uniform_divergence_is_divergence_times_area():
+    nx = ny = 48
+    P = _star(5, c=(23.7, 24.2))
+    sim = oracle.Sim(dict(nx=nx, ny=ny), bodies=[oracle.Body(R=P.copy())], sigma=_linear_sigma(nx, ny, 3e-4, -1e-4))
+    F = sim.body_force_area(0)
+    area = 0.5 * abs(np.sum(P[:-1, 0] * P[1:, 1] - P[1:, 0] * P[:-1, 1]) + P[-1, 0] * P[0, 1] - P[0, 0] * P[-1, 1])
+    assert abs(F[0] - 2e-4 * area) < 1e-15 * area and abs(F[1]) < 1e-18
+
+
+def test_area_force_is_continuous_in_the_nodes_unlike_the_site_sum():
+    rng = np.random.default_rng(9)
+    sig = rng.standard_normal((3, 40, 40)) * 1e-3
+    P = _star(7, c=(19.5, 20.5))
+    jumps_area, jumps_site = [], []
+    for k in range(40):
+        d = 0.01 * k
+        s = oracle.Sim(dict(nx=40, ny=40), bodies=[oracle.Body(R=P + [d, 0.3 * d])], sigma=sig)
+        jumps_area.append(s.body_force_area(0))
+        jumps_site.append(s.body_force(0)[:2])
+    da = np.abs(np.diff(np.array(jumps_area), axis=0)).max()
+    ds = np.abs(np.diff(np.array(jumps_site), axis=0)).max()
+    # a 0.01 shift moves O(0.01 * perimeter) of area: the area form changes by about that times
+    # |div sigma|, the site sum jumps by whole sites
+    assert da < 0.2 * ds
+    assert da < 0.01 * 2 * math.pi * 6 * 4e-3
