@@ -8,9 +8,10 @@ namespace lbk {
 constexpr int kMaxNodes = 1024;     // nodes per body
 constexpr int kMaxBodies = 64;      // bodies per simulation
 constexpr int kPatchTile = 16;      // immersed-boundary gather block: 16 x 16 patch sites
+constexpr int kItemBodies = 8;      // bodies listed per fused work item (more: scan all of them)
 constexpr int kBodyOut = 8;         // doubles per body written by the observable kernel
 constexpr int kMaxCand = 512;       // nodes whose footprint can reach one gather block
-constexpr int kTab = 4096;          // stiffness-table intervals over s = |P|^2 in [0, P_clamp^2]
+constexpr int kStiffSeg = 64;       // stiffness-table segments over s = |P|^2 in [0, P_clamp^2]
 constexpr int kHalo = 4;            // fused kernel: polarization halo depth (stress and h use 3)
 constexpr int kDefaultShift = 10;   // FP16 storage: offsets scaled by 2^10
 
@@ -32,7 +33,7 @@ struct SimDev {
     float inv_scale, scale;         // FP16 storage scale 2^-S and 2^S (1 for FP32)
     int ericksen;
     int pad0;
-    const float4 *tab;              // per interval: (A2, dA2, A4, dA4), A2 = a2/s, A4 = a4/s^2
+    const float *tab;               // per segment 8 floats: cubics in the local coordinate of A2 = a2/s, A4 = a4/s^2
     void *h[2];                     // post-collision population offsets, 9 planes (float or half)
     float *sig[2];                  // polymer stress planes sxx, syy, sxy
     double *P[2];                   // polarization planes Px, Py; FP64 because its per-step

@@ -42,13 +42,26 @@ template <typename T> __device__ __forceinline__ LBK_GLOBAL T *at32(T *base, uns
     return (LBK_GLOBAL T *)((LBK_GLOBAL char *)base + i * (unsigned)sizeof(T));
 }
 
+// Raw: the stored word, fetched one iteration ahead and converted only when used, so a prefetch
+// does not wait for its own load.
 template <> struct Pop<float> {
+    typedef float Raw;
+    static __device__ __forceinline__ Raw ld_raw(const float *p, unsigned i) { return *at32(p, i); }
+    static __device__ __forceinline__ float cvt(Raw r, float) { return r; }
     static __device__ __forceinline__ float load(const float *p, size_t i, float) { return p[i]; }
     static __device__ __forceinline__ void store(float *p, size_t i, float v, float) { p[i] = v; }
     static __device__ __forceinline__ float ld(const float *p, unsigned i, float) { return *at32(p, i); }
     static __device__ __forceinline__ void st(float *p, unsigned i, float v, float) { *at32(p, i) = v; }
 };
 template <> struct Pop<__half> {
+    // a 32-bit word per value: 16-bit values would be packed in pairs, which waits for both loads
+    typedef unsigned Raw;
+    static __device__ __forceinline__ Raw ld_raw(const __half *p, unsigned i) {
+        return *at32(reinterpret_cast<const unsigned short *>(p), i);
+    }
+    static __device__ __forceinline__ float cvt(Raw r, float inv_scale) {
+        return __half2float(__ushort_as_half((unsigned short)r)) * inv_scale;
+    }
     static __device__ __forceinline__ float load(const __half *p, size_t i, float inv_scale) {
         return __half2float(p[i]) * inv_scale;
     }
@@ -74,7 +87,7 @@ __device__ __forceinline__ void collide(float d[9], float Fx, float Fy, float om
     float jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]) + 0.5f * Fx;
     float jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]) + 0.5f * Fy;
     float rho = 1.0f + drho;
-    float ir = 1.0f / rho;
+    float ir = __builtin_amdgcn_rcpf(rho);   // 1 ulp; rho is within a few per cent of 1
     ux = jx * ir;
     uy = jy * ir;
     float uu15 = 1.5f * (ux * ux + uy * uy);
@@ -90,24 +103,27 @@ __device__ __forceinline__ void collide(float d[9], float Fx, float Fy, float om
     }
 }
 
-// ---- stiffness C~(P) (App. B) via tables of a2/s and a4/s^2 in s = |P|^2 ------------------
+// ---- stiffness C~(P) (App. B) via piecewise cubics of a2/s and a4/s^2 in s = |P|^2 ---------
 // a2 cos(2 th) = A2 (Px^2 - Py^2), a2 sin(2 th) = A2 2 Px Py, and the same for a4 with the
 // squares of those harmonics, so no angle and no division by |P| are needed.
 struct Stiff {
     float X1, X2, Y1, Y2;   // a4 c4 cA, a2 c2 cB, a4 s4 cA, a2 s2 cB
 };
 
-__device__ __forceinline__ Stiff stiffness(const SimDev &S, float Px, float Py) {
+// tab: kStiffSeg segments x two float4 (cubic coefficients c0..c3 of A2, then of A4), in LDS or
+// global memory
+template <typename Tab>
+__device__ __forceinline__ Stiff stiffness(const SimDev &S, Tab tab, float Px, float Py) {
     float sx = Px * Px, sy = Py * Py;
     float s = sx + sy;
     float A2, A4;
     if (s < S.smax) {
         float u = s * S.inv_ds;
-        int i = min((int)u, kTab - 1);
-        float fr = u - (float)i;
-        const LBK_GLOBAL float *t = (const LBK_GLOBAL float *)S.tab + 4 * i;
-        A2 = fmaf(fr, t[1], t[0]);
-        A4 = fmaf(fr, t[3], t[2]);
+        int i = min((int)u, kStiffSeg - 1);
+        float t = u - (float)i;
+        const float4 a = tab[2 * i], b = tab[2 * i + 1];
+        A2 = fmaf(fmaf(fmaf(a.w, t, a.z), t, a.y), t, a.x);
+        A4 = fmaf(fmaf(fmaf(b.w, t, b.z), t, b.y), t, b.x);
     } else {
         float r = S.smax / s;
         A2 = S.A2max * r;
@@ -245,6 +261,52 @@ __device__ __forceinline__ void ib_store_v(const SimDev &S, const BodyDev *bodie
         const BodyDev &B = bodies[S.b0 + b];
         int px = wrap_near(x - gptr(B.origin)[4 * parity + 2], S.nx);
         int py = wrap_near(y - gptr(B.origin)[4 * parity + 3], S.ny);
+        if ((unsigned)px < (unsigned)B.ps && (unsigned)py < (unsigned)B.ps) {
+            unsigned i = (unsigned)(py * B.ps + px);
+            gptr(B.vib)[i] = ux;
+            gptr(B.vib)[(unsigned)(B.ps * B.ps) + i] = uy;
+        }
+    }
+}
+
+// A body whose force/velocity patch touches a fused work item: the wrapped patch origin at the
+// current parity, the patch side and the patch planes.
+struct ItemBody {
+    int ox, oy, ps, pad;
+    const float *fib;
+    float *vib;
+};
+
+// do the periodic intervals [a, a + la) and [b, b + lb) on a ring of n sites intersect?
+// (0 <= a, b < n)
+__device__ __forceinline__ bool ring_overlap(int a, int la, int b, int lb, int n) {
+    if (la >= n || lb >= n) return true;
+    int d = b - a;
+    d = d < 0 ? d + n : d;
+    if (d < la) return true;
+    int e = a - b;
+    e = e < 0 ? e + n : e;
+    return e < lb;
+}
+
+__device__ __forceinline__ void ib_force_list(const ItemBody *L, int n, int nx, int ny, int x, int y, float &Fx,
+                                              float &Fy) {
+    for (int k = 0; k < n; ++k) {
+        const ItemBody &B = L[k];
+        int px = wrap_near(x - B.ox, nx), py = wrap_near(y - B.oy, ny);
+        if ((unsigned)px < (unsigned)B.ps && (unsigned)py < (unsigned)B.ps) {
+            unsigned i = (unsigned)(py * B.ps + px);
+            Fx += gptr(B.fib)[i];
+            Fy += gptr(B.fib)[(unsigned)(B.ps * B.ps) + i];
+        }
+    }
+}
+
+__device__ __forceinline__ void ib_store_v_list(const ItemBody *L, int n, int nx, int ny, int x, int y, float ux,
+                                                float uy) {
+    for (int k = 0; k < n; ++k) {
+        const ItemBody &B = L[k];
+        int px = wrap_near(x - B.ox, nx), py = wrap_near(y - B.oy, ny);
         if ((unsigned)px < (unsigned)B.ps && (unsigned)py < (unsigned)B.ps) {
             unsigned i = (unsigned)(py * B.ps + px);
             gptr(B.vib)[i] = ux;

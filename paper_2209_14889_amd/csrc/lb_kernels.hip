@@ -304,6 +304,9 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
     __shared__ float rV[2][2][T];    // velocity rows f-3 .. f-2
     __shared__ float rQs[2][3][T];   // predicted stress rows f-4 .. f-3
     __shared__ double rQp[2][2][T];  // predicted polarization rows f-4 .. f-3
+    __shared__ float4 sTab[2 * kStiffSeg];     // stiffness cubics of the item's simulation
+    __shared__ ItemBody sIB[kItemBodies];      // bodies whose patches touch the item
+    __shared__ int sNB;                        // their number, -1 if more than kItemBodies
     const int tid = threadIdx.x;
     const int nxt = cur ^ 1;
     if (blockIdx.x == 0 && tid == 0) d_t[0] = d_t[0] + 1;   // the body update after this step uses t+1
@@ -330,6 +333,32 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
         const bool colE = tid >= 4 && tid < wcol + 4;
         const float is = S.inv_scale, sc = S.scale;
 
+        // per-item constants: the stiffness cubics, and the bodies whose patches reach the rows
+        // y0-2 .. y0+l+1 and columns x0-4 .. x0+w+3 this item touches (wave 0 holds every body:
+        // at most kMaxBodies = 64 per simulation)
+        for (int q = tid; q < 2 * kStiffSeg; q += T) sTab[q] = reinterpret_cast<const float4 *>(S.tab)[q];
+        if (tid < 64) {
+            bool hit = false;
+            ItemBody ib{0, 0, 0, 0, nullptr, nullptr};
+            if (tid < S.nb) {
+                const BodyDev &B = bodies[S.b0 + tid];
+                ib.ox = gptr(B.origin)[4 * cur + 2];
+                ib.oy = gptr(B.origin)[4 * cur + 3];
+                ib.ps = B.ps;
+                ib.fib = B.fib;
+                ib.vib = B.vib;
+                hit = ring_overlap(ib.ox, ib.ps, wrapi(wi.x0 - kHalo, (int)nx), wi.w + 2 * kHalo, (int)nx) &&
+                      ring_overlap(ib.oy, ib.ps, wrapi(wi.y0 - 2, (int)ny), wi.l + 4, (int)ny);
+            }
+            const unsigned long long m = __ballot(hit);
+            const int cnt = __popcll(m);
+            if (hit) {
+                const int k = __popcll(m & ((1ull << tid) - 1ull));
+                if (k < kItemBodies) sIB[k] = ib;
+            }
+            if (tid == 0) sNB = cnt <= kItemBodies ? cnt : -1;
+        }
+
         // wrapped row indices relative to the front row f of the current iteration
         const int f0 = wi.y0 - 4;
         unsigned rp1 = (unsigned)wrapi(f0 + 1, (int)ny), r0 = (unsigned)wrapi(f0, (int)ny);
@@ -339,7 +368,7 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
         // rows the next iteration commits to LDS, loaded one iteration ahead
         double qP0 = 0.0, qP1 = 0.0;
         float qS0 = 0.f, qS1 = 0.f, qS2 = 0.f;
-        float qH[9];
+        typename Pop<HT>::Raw qH[9];
         if (colA) {
             const unsigned iP = r0 * nx + x, iS = rm1 * nx + x;
             qP0 = ld32(Pi, iP);
@@ -349,7 +378,7 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             qS2 = ld32(sgi, 2u * N + iS);
         }
 #pragma unroll
-        for (int q = 0; q < 9; ++q) qH[q] = 0.f;
+        for (int q = 0; q < 9; ++q) qH[q] = 0;
 
         // row f-4 of this column, frozen at time t (stage D of the previous iteration): the
         // corrector's inputs and the south neighbours of stage D
@@ -364,6 +393,7 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
         double qp0 = 0.0, qp1 = 0.0;
 
         __syncthreads();
+        const int nib = sNB;
         const int niter = wi.l + 8;
         for (int j = 0; j < niter; ++j) {
             const int a0 = j & 3, a1 = (j + 3) & 3, a2 = (j + 2) & 3, a3 = (j + 1) & 3;   // P rows f .. f-3
@@ -381,7 +411,7 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             }
             float d[9];
 #pragma unroll
-            for (int q = 0; q < 9; ++q) d[q] = qH[q];
+            for (int q = 0; q < 9; ++q) d[q] = Pop<HT>::cvt(qH[q], is);
             // prefetch for iteration j+1: P(f+1), sigma(f), and the populations pulled into row
             // f-1: h_n(x, r) = h*_n(x - c_n, r - c_n) from rows f-2, f-1, f
             if (j + 1 < niter) {
@@ -395,15 +425,15 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                 }
                 if (j + 1 >= 4 && colC) {
                     const unsigned yc = rm1 * nx, ym = rm2 * nx, yp = r0 * nx;
-                    qH[0] = Pop<HT>::ld(hin, yc + x, is);
-                    qH[1] = Pop<HT>::ld(hin, N + yc + xm, is);
-                    qH[2] = Pop<HT>::ld(hin, 2u * N + ym + x, is);
-                    qH[3] = Pop<HT>::ld(hin, 3u * N + yc + xp, is);
-                    qH[4] = Pop<HT>::ld(hin, 4u * N + yp + x, is);
-                    qH[5] = Pop<HT>::ld(hin, 5u * N + ym + xm, is);
-                    qH[6] = Pop<HT>::ld(hin, 6u * N + ym + xp, is);
-                    qH[7] = Pop<HT>::ld(hin, 7u * N + yp + xp, is);
-                    qH[8] = Pop<HT>::ld(hin, 8u * N + yp + xm, is);
+                    qH[0] = Pop<HT>::ld_raw(hin, yc + x);
+                    qH[1] = Pop<HT>::ld_raw(hin, N + yc + xm);
+                    qH[2] = Pop<HT>::ld_raw(hin, 2u * N + ym + x);
+                    qH[3] = Pop<HT>::ld_raw(hin, 3u * N + yc + xp);
+                    qH[4] = Pop<HT>::ld_raw(hin, 4u * N + yp + x);
+                    qH[5] = Pop<HT>::ld_raw(hin, 5u * N + ym + xm);
+                    qH[6] = Pop<HT>::ld_raw(hin, 6u * N + ym + xp);
+                    qH[7] = Pop<HT>::ld_raw(hin, 7u * N + yp + xp);
+                    qH[8] = Pop<HT>::ld_raw(hin, 8u * N + yp + xm);
                 }
             }
             __syncthreads();
@@ -436,7 +466,10 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                     Fx += 0.5f * (rE[o0][0][tid + 1] - rE[o0][0][tid - 1]) + 0.5f * (exy1 - exy3);
                     Fy += 0.5f * (rE[o0][1][tid + 1] - rE[o0][1][tid - 1]) + 0.5f * (eyy1 - eyy3);
                 }
-                if (S.nb) ib_force(S, bodies, cur, (int)x, (int)rm2, Fx, Fy);
+                if (nib > 0)
+                    ib_force_list(sIB, nib, (int)nx, (int)ny, (int)x, (int)rm2, Fx, Fy);
+                else if (nib < 0)
+                    ib_force(S, bodies, cur, (int)x, (int)rm2, Fx, Fy);
                 float drho, ux, uy;
                 collide(d, Fx, Fy, S.omega, S.guo, drho, ux, uy);
                 rV[o0][0][tid] = ux;
@@ -446,7 +479,10 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                     const unsigned o = rm2 * nx + x;
 #pragma unroll
                     for (int q = 0; q < 9; ++q) Pop<HT>::st(hout, (unsigned)q * N + o, d[q], sc);
-                    if (S.nb) ib_store_v(S, bodies, cur, (int)x, (int)rm2, ux, uy);
+                    if (nib > 0)
+                        ib_store_v_list(sIB, nib, (int)nx, (int)ny, (int)x, (int)rm2, ux, uy);
+                    else if (nib < 0)
+                        ib_store_v(S, bodies, cur, (int)x, (int)rm2, ux, uy);
                 }
             }
             __syncthreads();
@@ -470,7 +506,7 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                     double Pw[2] = {rP[a3][0][tid - 1], rP[a3][1][tid - 1]};
                     double Pn[2] = {rP[a2][0][tid], rP[a2][1][tid]};
                     double Ps[2] = {cp0, cp1};
-                    nk = stiffness(S, (float)Pc[0], (float)Pc[1]);
+                    nk = stiffness(S, sTab, (float)Pc[0], (float)Pc[1]);
                     float Xe[3], Xw[3], Xn[3], Rs[3];
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
@@ -687,7 +723,7 @@ __global__ __launch_bounds__(256) void k_mp_pred(const SimDev *__restrict__ sims
     gather3(S.sig[cur], N, q, X, Xe, Xw, Xn, Xs);
     double Y[2], Ye[2], Yw[2], Yn[2], Ys[2], Rp[2];
     gather2(S.P[cur], N, q, Y, Ye, Yw, Yn, Ys);
-    Stiff k = stiffness(S, (float)Y[0], (float)Y[1]);
+    Stiff k = stiffness(S, reinterpret_cast<const float4 *>(S.tab), (float)Y[0], (float)Y[1]);
     rhs_sigma(S, k, g, ux, uy, X, Xe, Xw, Xn, Xs, Rs);
     rhs_P(S, g, ux, uy, Y, Ye, Yw, Yn, Ys, Rp);
     for (int c = 0; c < 3; ++c) S.sps[c * N + q.c] = X[c] + Rs[c];
@@ -704,7 +740,7 @@ __global__ __launch_bounds__(256) void k_mp_corr(const SimDev *__restrict__ sims
     Grad g = grad_at(S, q);
     float ux = S.v[q.c], uy = S.v[N + q.c];
     const double *P = S.P[cur];
-    Stiff k = stiffness(S, (float)P[q.c], (float)P[N + q.c]);
+    Stiff k = stiffness(S, reinterpret_cast<const float4 *>(S.tab), (float)P[q.c], (float)P[N + q.c]);
     float X[3], Xe[3], Xw[3], Xn[3], Xs[3], Rs[3];
     gather3(S.sps, N, q, X, Xe, Xw, Xn, Xs);
     double Y[2], Ye[2], Yw[2], Yn[2], Ys[2], Rp[2];
