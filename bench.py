@@ -74,7 +74,8 @@ def counted_traffic(workload_name: str, shape: dict):
     summary (copy-kernel calibrated), or None when that summary is for another workload or launch
     shape, or the kernel sources changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"k_fused_{workload_name}_2048x2048_fp16_hbm_counters.json")
+    path = os.path.join(ROOT, "profiles",
+                        f"k_fused_{workload_name}_t{shape['threads']}_s{shape['seg_rows']}_hbm_counters.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -84,6 +85,85 @@ def counted_traffic(workload_name: str, shape: dict):
     if d["launch"]["threads"] != shape["threads"] or d["launch"]["seg_rows"] != shape["seg_rows"]:
         return None
     return round(d["traffic_bytes"] / 1e9, 4)
+
+
+def _db(path: str) -> str:
+    import glob
+    if path.endswith(".db"):
+        return path
+    found = sorted(glob.glob(os.path.join(path, "**", "*_results.db"), recursive=True))
+    if not found:
+        raise SystemExit(f"no rocprofv3 results database under {path}")
+    return found[0]
+
+
+def _counter_kib(db: str, kernel_prefix: str):
+    """Mean counter value (KiB) per dispatch of the kernels whose name starts with kernel_prefix."""
+    import sqlite3
+    con = sqlite3.connect(_db(db))
+    rows = con.execute("select kernel_name, counter_name, value from counters_collection").fetchall()
+    vals = [v for k, c, v in rows if k.startswith(kernel_prefix)]
+    if not vals:
+        raise SystemExit(f"no dispatch of {kernel_prefix} in {db}")
+    return sum(vals) / len(vals), len(vals), rows[0][1]
+
+
+def counters_summary(outdir: str, workload_name: str, threads: int, seg_rows: int, command: str):
+    """Turn four rocprofv3 --pmc runs (copy FETCH_SIZE, copy WRITE_SIZE, fused FETCH_SIZE, fused
+    WRITE_SIZE, in <outdir>/pmc_copy_f, pmc_copy_w, pmc_<workload>_f, pmc_<workload>_w) into the
+    calibrated HBM traffic of one fused launch of the given shape:
+    profiles/k_fused_<workload>_t<threads>_s<seg_rows>_hbm_counters.{json,md}."""
+    import hashlib
+    copy_bytes = 64 * 1024 * 1024 * 4
+    cf, _, _ = _counter_kib(os.path.join(outdir, "pmc_copy_f"), "__amd_rocclr_copyBuffer")
+    cw, _, _ = _counter_kib(os.path.join(outdir, "pmc_copy_w"), "__amd_rocclr_copyBuffer")
+    tag = f"{workload_name}_t{threads}_s{seg_rows}"
+    kf, nf, _ = _counter_kib(os.path.join(outdir, f"pmc_{tag}_f"), "void lbk::k_fused")
+    kw, nw, _ = _counter_kib(os.path.join(outdir, f"pmc_{tag}_w"), "void lbk::k_fused")
+    # the copy reads and writes copy_bytes once: the factors that turn each counter into bytes
+    fetch_scale = copy_bytes / (cf * 1024.0)
+    write_scale = copy_bytes / (cw * 1024.0)
+    w, _, precision = workload(workload_name, 1)
+    alg = bytes_per_site(precision) * w.sites
+    d = {
+        "kernel": "k_fused", "workload": workload_name, "launch": {"threads": threads, "seg_rows": seg_rows},
+        "copy_bytes": copy_bytes, "fetch_scale": fetch_scale, "write_scale": write_scale,
+        "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw, "dispatches": [nf, nw],
+        "fetch_bytes": kf * 1024.0 * fetch_scale, "write_bytes": kw * 1024.0 * write_scale,
+        "algorithmic_bytes": alg, "sources": KERNEL_SOURCES,
+        "sources_sha256": hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read()
+                                                  for p in KERNEL_SOURCES)).hexdigest(),
+    }
+    d["traffic_bytes"] = d["fetch_bytes"] + d["write_bytes"]
+    base = os.path.join(ROOT, "profiles", f"k_fused_{workload_name}_t{threads}_s{seg_rows}_hbm_counters")
+    with open(base + ".json", "w") as f:
+        json.dump(d, f, indent=1)
+    half = alg / 2
+    with open(base + ".md", "w") as f:
+        f.write(f"# HBM byte counters: k_fused, workload {workload_name} (threads {threads}, {seg_rows} rows per item)\n\n")
+        f.write("Commands (one counter per run, each run alone), then the summary:\n\n```\n" + command.strip() + "\n```\n\n")
+        f.write(f"Calibration: a {copy_bytes >> 20} MiB device copy reads FETCH_SIZE = {cf:.1f} KiB and writes "
+                f"WRITE_SIZE = {cw:.1f} KiB per dispatch: scale factors {fetch_scale:.4f} (fetch) and "
+                f"{write_scale:.4f} (write).\n\n")
+        f.write(f"k_fused per dispatch (mean of {nf} and {nw} dispatches): FETCH_SIZE = {kf:.1f} KiB -> "
+                f"{d['fetch_bytes'] / 1e6:.1f} MB; WRITE_SIZE = {kw:.1f} KiB -> {d['write_bytes'] / 1e6:.1f} MB.\n\n")
+        f.write(f"Algorithmic bytes: {bytes_per_site(precision)} B/site x {w.sites} sites = {alg / 1e6:.1f} MB per launch "
+                f"({half / 1e6:.1f} MB each way).\n\n")
+        f.write(f"Measured / algorithmic: reads {d['fetch_bytes'] / half:.3f}, writes {d['write_bytes'] / half:.3f}.\n")
+    log(f"bench: wrote {base}.json/.md")
+
+
+def trace_summary(db: str, title: str, command: str, out: str, top: int = 8):
+    """Markdown table of the rocprofv3 --kernel-trace --stats top kernels (name, calls, mean us, %)."""
+    import sqlite3
+    con = sqlite3.connect(_db(db))
+    rows = con.execute("select name, total_calls, total_duration, average, percentage from top_kernels").fetchall()
+    with open(os.path.join(ROOT, "profiles", out), "w") as f:
+        f.write(f"# {title}\n\nCommand:\n\n```\n{command.strip()}\n```\n\n")
+        f.write("| kernel | calls | total us | mean us | % |\n|---|---|---|---|---|\n")
+        for name, calls, tot, avg, pct in rows[:top]:
+            f.write(f"| `{name}` | {calls} | {tot:.1f} | {avg:.2f} | {pct:.1f} |\n")
+    log(f"bench: wrote profiles/{out}")
 
 
 def cpu_baseline(w, name: str, budget_s: float = 15.0):
@@ -126,9 +206,25 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate leg (4096 + 512 LB runs of 128^2, network training, fallback)")
+    ap.add_argument("--counters-summary", default="",
+                    help="directory holding rocprofv3 --pmc outputs pmc_copy_f/w and "
+                         "pmc_<workload>_t<threads>_s<seg_rows>_f/w: "
+                         "write the calibrated HBM traffic summary under profiles/ (no GPU use)")
+    ap.add_argument("--trace-summary", default="", help="rocprofv3 --kernel-trace --stats output: write a "
+                    "markdown table of its top kernels to profiles/<--summary-name> (no GPU use)")
+    ap.add_argument("--summary-name", default="")
+    ap.add_argument("--summary-title", default="")
+    ap.add_argument("--summary-command", default="", help="the command that produced the profiler output")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB device buffer 5 times (reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.counters_summary:
+        counters_summary(args.counters_summary, args.workload, args.threads, args.seg_rows, args.summary_command)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary, args.summary_title or args.summary_name, args.summary_command,
+                      args.summary_name)
+        return
     if args.copy_calibration:
         import torch
         n = 64 * 1024 * 1024
