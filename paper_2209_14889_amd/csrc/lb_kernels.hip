@@ -326,7 +326,6 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
         const unsigned x = (unsigned)wrapi(c, (int)nx), xm = (unsigned)wrapi(c - 1, (int)nx),
                        xp = (unsigned)wrapi(c + 1, (int)nx);
         const int wcol = wi.w;
-        const bool colA = tid < wcol + 2 * kHalo;
         const bool colB = tid >= 1 && tid < wcol + 7;
         const bool colC = tid >= 2 && tid < wcol + 6;
         const bool colD = tid >= 3 && tid < wcol + 5;
@@ -365,75 +364,76 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
         unsigned rm1 = (unsigned)wrapi(f0 - 1, (int)ny), rm2 = (unsigned)wrapi(f0 - 2, (int)ny);
         unsigned rm4 = (unsigned)wrapi(f0 - 4, (int)ny);
 
-        // rows the next iteration commits to LDS, loaded one iteration ahead
-        double qP0 = 0.0, qP1 = 0.0;
-        float qS0 = 0.f, qS1 = 0.f, qS2 = 0.f;
-        typename Pop<HT>::Raw qH[9];
-        if (colA) {
+        // Loads for the next iteration, issued one iteration ahead.  Every lane loads (all
+        // indices are wrapped into the lattice); lanes outside a stage's columns never use them.
+        struct Pre {
+            double P0, P1;                 // P(f+1)
+            float S0, S1, S2;              // sigma(f)
+            typename Pop<HT>::Raw H[9];    // populations pulled into row f-1
+        };
+        // Values of this column handed from one iteration to the next: stage D's centre row
+        // (the corrector's frozen inputs and the next predictor's south neighbours) and stage E's
+        // predicted centre (the next corrector's south neighbour).
+        struct Carry {
+            float vx, vy, s0, s1, s2;
+            double p0, p1;
+            Grad g;
+            Stiff k;
+            float q0, q1, q2;
+            double qp0, qp1;
+        };
+        Pre preA, preB;
+        Carry carA, carB;
+        {
             const unsigned iP = r0 * nx + x, iS = rm1 * nx + x;
-            qP0 = ld32(Pi, iP);
-            qP1 = ld32(Pi, N + iP);
-            qS0 = ld32(sgi, iS);
-            qS1 = ld32(sgi, N + iS);
-            qS2 = ld32(sgi, 2u * N + iS);
+            preA.P0 = ld32(Pi, iP);
+            preA.P1 = ld32(Pi, N + iP);
+            preA.S0 = ld32(sgi, iS);
+            preA.S1 = ld32(sgi, N + iS);
+            preA.S2 = ld32(sgi, 2u * N + iS);
         }
-#pragma unroll
-        for (int q = 0; q < 9; ++q) qH[q] = 0;
-
-        // row f-4 of this column, frozen at time t (stage D of the previous iteration): the
-        // corrector's inputs and the south neighbours of stage D
-        float cvx = 0.f, cvy = 0.f, cs0 = 0.f, cs1 = 0.f, cs2 = 0.f;
-        double cp0 = 0.0, cp1 = 0.0;
-        Grad cg = {0.f, 0.f, 0.f, 0.f};
-        Stiff ck = {0.f, 0.f, 0.f, 0.f};
         // Ericksen xy, yy of this column at rows f-1, f-2, f-3
         float exy1 = 0.f, eyy1 = 0.f, exy2 = 0.f, eyy2 = 0.f, exy3 = 0.f, eyy3 = 0.f;
-        // predicted stress and polarization of this column one row below the corrector row
-        float qs0 = 0.f, qs1 = 0.f, qs2 = 0.f;
-        double qp0 = 0.0, qp1 = 0.0;
 
         __syncthreads();
         const int nib = sNB;
         const int niter = wi.l + 8;
-        for (int j = 0; j < niter; ++j) {
+
+        // one row iteration j; pin/cin were filled by iteration j-1, pout/cout are for j+1
+        auto iterate = [&](const int j, const Pre &pin, Pre &pout, const Carry &cin, Carry &cout) {
             const int a0 = j & 3, a1 = (j + 3) & 3, a2 = (j + 2) & 3, a3 = (j + 1) & 3;   // P rows f .. f-3
             const int b1 = (j + 59) % 3, b2 = (j + 58) % 3, b3 = (j + 57) % 3;           // stress rows f-1 .. f-3
             const int o1 = (j + 1) & 1, o0 = j & 1;   // rows f-1 / f-3 (odd lag) and f-2 / f-4 (even lag)
-            const bool runC = j >= 4 && colC;
 
             // ---- stage A: commit P(f), sigma(f-1); take this iteration's populations
-            if (colA) {
-                rP[a0][0][tid] = qP0;
-                rP[a0][1][tid] = qP1;
-                rS[b1][0][tid] = qS0;
-                rS[b1][1][tid] = qS1;
-                rS[b1][2][tid] = qS2;
-            }
+            rP[a0][0][tid] = pin.P0;
+            rP[a0][1][tid] = pin.P1;
+            rS[b1][0][tid] = pin.S0;
+            rS[b1][1][tid] = pin.S1;
+            rS[b1][2][tid] = pin.S2;
             float d[9];
 #pragma unroll
-            for (int q = 0; q < 9; ++q) d[q] = Pop<HT>::cvt(qH[q], is);
+            for (int q = 0; q < 9; ++q) d[q] = Pop<HT>::cvt(pin.H[q], is);
             // prefetch for iteration j+1: P(f+1), sigma(f), and the populations pulled into row
             // f-1: h_n(x, r) = h*_n(x - c_n, r - c_n) from rows f-2, f-1, f
             if (j + 1 < niter) {
-                if (colA) {
-                    const unsigned iP = rp1 * nx + x, iS = r0 * nx + x;
-                    qP0 = ld32(Pi, iP);
-                    qP1 = ld32(Pi, N + iP);
-                    qS0 = ld32(sgi, iS);
-                    qS1 = ld32(sgi, N + iS);
-                    qS2 = ld32(sgi, 2u * N + iS);
-                }
-                if (j + 1 >= 4 && colC) {
+                const unsigned iP = rp1 * nx + x, iS = r0 * nx + x;
+                pout.P0 = ld32(Pi, iP);
+                pout.P1 = ld32(Pi, N + iP);
+                pout.S0 = ld32(sgi, iS);
+                pout.S1 = ld32(sgi, N + iS);
+                pout.S2 = ld32(sgi, 2u * N + iS);
+                if (j + 1 >= 4) {
                     const unsigned yc = rm1 * nx, ym = rm2 * nx, yp = r0 * nx;
-                    qH[0] = Pop<HT>::ld_raw(hin, yc + x);
-                    qH[1] = Pop<HT>::ld_raw(hin, N + yc + xm);
-                    qH[2] = Pop<HT>::ld_raw(hin, 2u * N + ym + x);
-                    qH[3] = Pop<HT>::ld_raw(hin, 3u * N + yc + xp);
-                    qH[4] = Pop<HT>::ld_raw(hin, 4u * N + yp + x);
-                    qH[5] = Pop<HT>::ld_raw(hin, 5u * N + ym + xm);
-                    qH[6] = Pop<HT>::ld_raw(hin, 6u * N + ym + xp);
-                    qH[7] = Pop<HT>::ld_raw(hin, 7u * N + yp + xp);
-                    qH[8] = Pop<HT>::ld_raw(hin, 8u * N + yp + xm);
+                    pout.H[0] = Pop<HT>::ld_raw(hin, yc + x);
+                    pout.H[1] = Pop<HT>::ld_raw(hin, N + yc + xm);
+                    pout.H[2] = Pop<HT>::ld_raw(hin, 2u * N + ym + x);
+                    pout.H[3] = Pop<HT>::ld_raw(hin, 3u * N + yc + xp);
+                    pout.H[4] = Pop<HT>::ld_raw(hin, 4u * N + yp + x);
+                    pout.H[5] = Pop<HT>::ld_raw(hin, 5u * N + ym + xm);
+                    pout.H[6] = Pop<HT>::ld_raw(hin, 6u * N + ym + xp);
+                    pout.H[7] = Pop<HT>::ld_raw(hin, 7u * N + yp + xp);
+                    pout.H[8] = Pop<HT>::ld_raw(hin, 8u * N + yp + xm);
                 }
             }
             __syncthreads();
@@ -459,7 +459,7 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             __syncthreads();
 
             // ---- stage C: force, moments, collision at row f-2
-            if (runC) {
+            if (j >= 4 && colC) {
                 float Fx = 0.5f * (rS[b2][0][tid + 1] - rS[b2][0][tid - 1]) + 0.5f * (rS[b1][2][tid] - rS[b3][2][tid]);
                 float Fy = 0.5f * (rS[b2][2][tid + 1] - rS[b2][2][tid - 1]) + 0.5f * (rS[b1][1][tid] - rS[b3][1][tid]);
                 if (S.ericksen) {
@@ -488,25 +488,21 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             __syncthreads();
 
             // ---- stage D: predictor at row f-3 (from j = 5 only the carried centre values)
-            float nvx = 0.f, nvy = 0.f, ns0 = 0.f, ns1 = 0.f, ns2 = 0.f;
-            double np0 = 0.0, np1 = 0.0;
-            Grad ng = {0.f, 0.f, 0.f, 0.f};
-            Stiff nk = {0.f, 0.f, 0.f, 0.f};
             if (j >= 5 && colD) {
-                nvx = rV[o1][0][tid];
-                nvy = rV[o1][1][tid];
+                cout.vx = rV[o1][0][tid];
+                cout.vy = rV[o1][1][tid];
                 double Pc[2] = {rP[a3][0][tid], rP[a3][1][tid]};
                 float X[3];
 #pragma unroll
                 for (int q = 0; q < 3; ++q) X[q] = rS[b3][q][tid];
                 if (j >= 6) {
-                    ng = grad_v(rV[o1][0][tid + 1], rV[o1][0][tid - 1], rV[o0][0][tid], cvx,
-                                rV[o1][1][tid + 1], rV[o1][1][tid - 1], rV[o0][1][tid], cvy);
+                    cout.g = grad_v(rV[o1][0][tid + 1], rV[o1][0][tid - 1], rV[o0][0][tid], cin.vx,
+                                    rV[o1][1][tid + 1], rV[o1][1][tid - 1], rV[o0][1][tid], cin.vy);
                     double Pe[2] = {rP[a3][0][tid + 1], rP[a3][1][tid + 1]};
                     double Pw[2] = {rP[a3][0][tid - 1], rP[a3][1][tid - 1]};
                     double Pn[2] = {rP[a2][0][tid], rP[a2][1][tid]};
-                    double Ps[2] = {cp0, cp1};
-                    nk = stiffness(S, sTab, (float)Pc[0], (float)Pc[1]);
+                    double Ps[2] = {cin.p0, cin.p1};
+                    cout.k = stiffness(S, sTab, (float)Pc[0], (float)Pc[1]);
                     float Xe[3], Xw[3], Xn[3], Rs[3];
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
@@ -514,21 +510,21 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                         Xw[q] = rS[b3][q][tid - 1];
                         Xn[q] = rS[b2][q][tid];
                     }
-                    const float Xs[3] = {cs0, cs1, cs2};
-                    rhs_sigma(S, nk, ng, nvx, nvy, X, Xe, Xw, Xn, Xs, Rs);
+                    const float Xs[3] = {cin.s0, cin.s1, cin.s2};
+                    rhs_sigma(S, cout.k, cout.g, cout.vx, cout.vy, X, Xe, Xw, Xn, Xs, Rs);
                     double Rp[2];
-                    rhs_P(S, ng, nvx, nvy, Pc, Pe, Pw, Pn, Ps, Rp);
+                    rhs_P(S, cout.g, cout.vx, cout.vy, Pc, Pe, Pw, Pn, Ps, Rp);
                     rQs[o1][0][tid] = X[0] + Rs[0];
                     rQs[o1][1][tid] = X[1] + Rs[1];
                     rQs[o1][2][tid] = X[2] + Rs[2];
                     rQp[o1][0][tid] = Pc[0] + Rp[0];
                     rQp[o1][1][tid] = Pc[1] + Rp[1];
                 }
-                ns0 = X[0];
-                ns1 = X[1];
-                ns2 = X[2];
-                np0 = Pc[0];
-                np1 = Pc[1];
+                cout.s0 = X[0];
+                cout.s1 = X[1];
+                cout.s2 = X[2];
+                cout.p0 = Pc[0];
+                cout.p1 = Pc[1];
             }
             __syncthreads();
 
@@ -548,44 +544,40 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                         Xw[q] = rQs[o0][q][tid - 1];
                         Xn[q] = rQs[o1][q][tid];
                     }
-                    const float Xs[3] = {qs0, qs1, qs2};
-                    rhs_sigma(S, ck, cg, cvx, cvy, X, Xe, Xw, Xn, Xs, Rs);
+                    const float Xs[3] = {cin.q0, cin.q1, cin.q2};
+                    rhs_sigma(S, cin.k, cin.g, cin.vx, cin.vy, X, Xe, Xw, Xn, Xs, Rs);
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
                         Ye[q] = rQp[o0][q][tid + 1];
                         Yw[q] = rQp[o0][q][tid - 1];
                         Yn[q] = rQp[o1][q][tid];
                     }
-                    const double Ys[2] = {qp0, qp1};
-                    rhs_P(S, cg, cvx, cvy, Y, Ye, Yw, Yn, Ys, Rp);
+                    const double Ys[2] = {cin.qp0, cin.qp1};
+                    rhs_P(S, cin.g, cin.vx, cin.vy, Y, Ye, Yw, Yn, Ys, Rp);
                     const unsigned o = rm4 * nx + x;
-                    st32(sgo, o, 0.5f * ((cs0 + X[0]) + Rs[0]));
-                    st32(sgo, N + o, 0.5f * ((cs1 + X[1]) + Rs[1]));
-                    st32(sgo, 2u * N + o, 0.5f * ((cs2 + X[2]) + Rs[2]));
-                    st32(Po, o, 0.5 * ((cp0 + Y[0]) + Rp[0]));
-                    st32(Po, N + o, 0.5 * ((cp1 + Y[1]) + Rp[1]));
+                    st32(sgo, o, 0.5f * ((cin.s0 + X[0]) + Rs[0]));
+                    st32(sgo, N + o, 0.5f * ((cin.s1 + X[1]) + Rs[1]));
+                    st32(sgo, 2u * N + o, 0.5f * ((cin.s2 + X[2]) + Rs[2]));
+                    st32(Po, o, 0.5 * ((cin.p0 + Y[0]) + Rp[0]));
+                    st32(Po, N + o, 0.5 * ((cin.p1 + Y[1]) + Rp[1]));
                 }
-                qs0 = X[0];
-                qs1 = X[1];
-                qs2 = X[2];
-                qp0 = Y[0];
-                qp1 = Y[1];
+                cout.q0 = X[0];
+                cout.q1 = X[1];
+                cout.q2 = X[2];
+                cout.qp0 = Y[0];
+                cout.qp1 = Y[1];
             }
-            // row f-3 becomes next iteration's row f-4
-            cvx = nvx;
-            cvy = nvy;
-            cg = ng;
-            ck = nk;
-            cs0 = ns0;
-            cs1 = ns1;
-            cs2 = ns2;
-            cp0 = np0;
-            cp1 = np1;
             inc_row(rp1, ny);
             inc_row(r0, ny);
             inc_row(rm1, ny);
             inc_row(rm2, ny);
             inc_row(rm4, ny);
+        };
+
+        // two iterations per trip with the register sets swapped, so no values are copied
+        for (int j = 0; j < niter; j += 2) {
+            iterate(j, preA, preB, carA, carB);
+            if (j + 1 < niter) iterate(j + 1, preB, preA, carB, carA);
         }
     }
 }
