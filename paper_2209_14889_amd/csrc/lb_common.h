@@ -8,6 +8,7 @@ namespace lbk {
 constexpr int kMaxNodes = 1024;     // nodes per body
 constexpr int kMaxBodies = 64;      // bodies per simulation
 constexpr int kPatchTile = 16;      // immersed-boundary gather block: 16 x 16 patch sites
+constexpr int kIbOneLaunchTiles = 512;   // up to this many patch tiles: body update in one launch
 constexpr int kItemBodies = 8;      // bodies listed per fused work item (more: scan all of them)
 constexpr int kBodyOut = 8;         // doubles per body written by the observable kernel
 constexpr int kMaxCand = 512;       // nodes whose footprint can reach one gather block

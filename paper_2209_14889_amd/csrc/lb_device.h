@@ -90,16 +90,21 @@ __device__ __forceinline__ void collide(float d[9], float Fx, float Fy, float om
     float ir = __builtin_amdgcn_rcpf(rho);   // 1 ulp; rho is within a few per cent of 1
     ux = jx * ir;
     uy = jy * ir;
-    float uu15 = 1.5f * (ux * ux + uy * uy);
-    float uF = ux * Fx + uy * Fy;
+    // d' = (1 - omega) d + omega deq + src with, per direction n (t = c_n.u, g = c_n.F),
+    //   deq = w_n (drho + rho (3 t + 4.5 t^2 - 1.5 u.u)),  src = guo w_n (3 (g - u.F) + 9 t g),
+    // gathered as w_n (C0 + t (a1 + a2 t) + g (b1 + b2 t)) with per-site a1, a2, C0
+    const float uu15 = 1.5f * (ux * ux + uy * uy);
+    const float uF = ux * Fx + uy * Fy;
+    const float orho = omega * rho;
+    const float a1 = 3.0f * orho, a2 = 4.5f * orho, b1 = 3.0f * guo, b2 = 9.0f * guo;
+    const float C0 = omega * drho - orho * uu15 - b1 * uF;
+    const float keep = 1.0f - omega;
 #pragma unroll
     for (int n = 0; n < 9; ++n) {
-        float cu = kCX[n] * ux + kCY[n] * uy;
-        float cF = kCX[n] * Fx + kCY[n] * Fy;
-        // equilibrium offset: w (rho (1 + 3cu + 4.5cu^2 - 1.5u^2) - 1)
-        float deq = kW[n] * (drho + rho * (cu * (3.0f + 4.5f * cu) - uu15));
-        float src = guo * kW[n] * (3.0f * (cF - uF) + 9.0f * cu * cF);
-        d[n] = d[n] + omega * (deq - d[n]) + src;
+        const float t = kCX[n] * ux + kCY[n] * uy;
+        const float g = kCX[n] * Fx + kCY[n] * Fy;
+        const float r = fmaf(t, fmaf(a2, t, a1), fmaf(g, fmaf(b2, t, b1), C0));
+        d[n] = fmaf(keep, d[n], kW[n] * r);
     }
 }
 

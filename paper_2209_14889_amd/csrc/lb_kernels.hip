@@ -118,6 +118,7 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Two-launch body update for many bodies (each node advanced once): k_ib_nodes, then k_ib_spread.
 // One block per body.  ADVANCE: move the nodes from R(t) to R(t+1) by Heun with the velocity patch
 // written during step t (App. A: overdamped, no slip); otherwise take R[cur] as it is.  Then the
 // node forces at the new positions with the pull at time *d_t, the new patch origin, and each
@@ -276,6 +277,153 @@ __global__ __launch_bounds__(256) void k_ib_spread(const BodyDev *__restrict__ b
         B.fib[(unsigned)(B.ps * B.ps) + i] = (float)fy;
     }
     if (bad) atomicOr(d_status, kStatusPatch);
+}
+
+// Body update and force spreading in one launch, one 256-thread block per (body, 16x16 tile of
+// its patch).  Every block of a body repeats the node update (a few hundred nodes):
+//  ADVANCE: move the nodes from R(t) to R(t+1) by Heun with the velocity patch written during
+//  step t (App. A: overdamped, no slip); otherwise take R[cur] as it is;
+//  the patch origin for the new positions (3 sites of margin around the nodes);
+//  the forces of the nodes whose 4x4 footprint reaches the tile, at the new positions with the
+//  pull at time *d_t, gathered onto the tile's sites in node order (deterministic):
+//  f_IB(r) = sum_a f_a phi phi (App. A).
+// Tile 0 of each body publishes the new positions, all node forces and the origin; the other
+// blocks only read the current-parity buffers, so blocks never wait on each other.
+template <bool ADVANCE>
+__global__ __launch_bounds__(256) void k_ib_step(const SimDev *__restrict__ sims, BodyDev *__restrict__ bodies,
+                                                 const int2 *__restrict__ blk, int cur, const int *__restrict__ d_t,
+                                                 int *__restrict__ d_status) {
+    __shared__ double2 sR[kMaxNodes];
+    __shared__ double sRed[4][4];
+    __shared__ int2 sI[kMaxCand];
+    __shared__ float4 sW[kMaxCand][2];
+    __shared__ double2 sF[kMaxCand];
+    __shared__ int sCnt[4];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int2 bt = blk[blockIdx.x];
+    BodyDev &B = bodies[bt.x];
+    const SimDev &S = sims[B.sim];
+    const int n = B.n;
+    const int dst = ADVANCE ? (cur ^ 1) : cur;
+    const bool lead = bt.y == 0;
+    bool bad = false;        // node outside its patch (every block finds the same; tile 0 reports)
+    bool overflow = false;   // more footprints reach this tile than it can list
+
+    const double2 *Rc = reinterpret_cast<const double2 *>(B.R[cur]);
+    int ox = 0, oy = 0;
+    if (ADVANCE) {
+        ox = B.origin[4 * cur];
+        oy = B.origin[4 * cur + 1];
+    }
+    double mnx = 1e300, mny = 1e300, mxx = -1e300, mxy = -1e300;
+    for (int a = tid; a < n; a += 256) {
+        double2 R = Rc[a];
+        if (ADVANCE) {
+            double v1x, v1y, v2x, v2y;
+            interp_patch(B, ox, oy, R.x, R.y, v1x, v1y, bad);
+            interp_patch(B, ox, oy, R.x + v1x, R.y + v1y, v2x, v2y, bad);
+            R.x += 0.5 * (v1x + v2x);
+            R.y += 0.5 * (v1y + v2y);
+        }
+        sR[a] = R;
+        mnx = fmin(mnx, R.x);
+        mny = fmin(mny, R.y);
+        mxx = fmax(mxx, R.x);
+        mxy = fmax(mxy, R.y);
+    }
+    mnx = wave_min(mnx);
+    mny = wave_min(mny);
+    mxx = wave_max(mxx);
+    mxy = wave_max(mxy);
+    if (lane == 0) {
+        sRed[wv][0] = mnx;
+        sRed[wv][1] = mny;
+        sRed[wv][2] = mxx;
+        sRed[wv][3] = mxy;
+    }
+    __syncthreads();
+    mnx = fmin(fmin(sRed[0][0], sRed[1][0]), fmin(sRed[2][0], sRed[3][0]));
+    mny = fmin(fmin(sRed[0][1], sRed[1][1]), fmin(sRed[2][1], sRed[3][1]));
+    mxx = fmax(fmax(sRed[0][2], sRed[1][2]), fmax(sRed[2][2], sRed[3][2]));
+    mxy = fmax(fmax(sRed[0][3], sRed[1][3]), fmax(sRed[2][3], sRed[3][3]));
+    // patch: 3 sites of margin below the lowest node cover the kernel support (2) plus one site of
+    // node motion; the same margin above is checked against the patch side
+    const int nox = (int)floor(mnx) - 3, noy = (int)floor(mny) - 3;
+    if ((int)floor(mxx) + 3 - nox >= B.ps || (int)floor(mxy) + 3 - noy >= B.ps) bad = true;
+
+    const double pf = pull_factor(B, (double)d_t[0]);
+    if (lead) {
+        double2 *Fn = reinterpret_cast<double2 *>(B.fnode);
+        double2 *Rd = reinterpret_cast<double2 *>(B.R[dst]);
+        for (int a = tid; a < n; a += 256) {
+            Fn[a] = node_force(B, sR, a, pf);
+            if (ADVANCE) Rd[a] = sR[a];
+        }
+        if (tid == 0) {
+            B.origin[4 * dst] = nox;
+            B.origin[4 * dst + 1] = noy;
+            B.origin[4 * dst + 2] = wrapi(nox, S.nx);
+            B.origin[4 * dst + 3] = wrapi(noy, S.ny);
+        }
+    }
+
+    // nodes whose footprint reaches this tile, compacted in node order
+    const int tx = bt.y % B.nside, ty = bt.y / B.nside;
+    const int X0 = nox + tx * kPatchTile, Y0 = noy + ty * kPatchTile;
+    int tot = 0;
+    for (int base = 0; base < n; base += 256) {
+        const int a = base + tid;
+        bool flag = false;
+        int ix = 0, iy = 0;
+        float wx[4], wy[4];
+        if (a < n) {
+            const double2 R = sR[a];
+            phi4(R.x, ix, wx);
+            phi4(R.y, iy, wy);
+            flag = ix > X0 - 4 && ix < X0 + kPatchTile && iy > Y0 - 4 && iy < Y0 + kPatchTile;
+        }
+        const unsigned long long m = __ballot(flag);
+        const int pre = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) sCnt[wv] = __popcll(m);
+        __syncthreads();
+        int off = tot;
+        for (int w = 0; w < wv; ++w) off += sCnt[w];
+        if (flag) {
+            const int q = off + pre;
+            if (q < kMaxCand) {
+                sI[q] = make_int2(ix - X0, iy - Y0);
+                sW[q][0] = make_float4(wx[0], wx[1], wx[2], wx[3]);
+                sW[q][1] = make_float4(wy[0], wy[1], wy[2], wy[3]);
+                sF[q] = node_force(B, sR, a, pf);
+            } else {
+                overflow = true;
+            }
+        }
+        tot += sCnt[0] + sCnt[1] + sCnt[2] + sCnt[3];
+        __syncthreads();
+    }
+    const int cnt = min(tot, kMaxCand);
+    const int lx = tid % kPatchTile, ly = tid / kPatchTile;
+    const int px = tx * kPatchTile + lx, py = ty * kPatchTile + ly;
+    if (px < B.ps && py < B.ps) {
+        double fx = 0.0, fy = 0.0;
+        for (int q = 0; q < cnt; ++q) {
+            const int2 o = sI[q];
+            const int i = lx - o.x, jj = ly - o.y;
+            if ((unsigned)i < 4u && (unsigned)jj < 4u) {
+                const float4 wxv = sW[q][0], wyv = sW[q][1];
+                const float wxs = i == 0 ? wxv.x : i == 1 ? wxv.y : i == 2 ? wxv.z : wxv.w;
+                const float wys = jj == 0 ? wyv.x : jj == 1 ? wyv.y : jj == 2 ? wyv.z : wyv.w;
+                const double w = (double)wxs * (double)wys;
+                fx += sF[q].x * w;
+                fy += sF[q].y * w;
+            }
+        }
+        const unsigned i = (unsigned)(py * B.ps + px);
+        B.fib[i] = (float)fx;
+        B.fib[(unsigned)(B.ps * B.ps) + i] = (float)fy;
+    }
+    if ((bad && lead) || overflow) atomicOr(d_status, kStatusPatch);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -982,11 +1130,19 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ src, HT 
 hipError_t launch_ib(bool advance, int nbodies, int ntiles, hipStream_t st, const SimDev *sims, BodyDev *bodies,
                      const int2 *blk, int cur, const int *d_t, int *d_status) {
     if (nbodies <= 0) return hipSuccess;
-    if (advance)
-        k_ib_nodes<true><<<nbodies, 256, 0, st>>>(sims, bodies, cur, d_t, d_status);
-    else
-        k_ib_nodes<false><<<nbodies, 256, 0, st>>>(sims, bodies, cur, d_t, d_status);
-    k_ib_spread<<<ntiles, 256, 0, st>>>(bodies, blk, advance ? (cur ^ 1) : cur, d_status);
+    if (ntiles <= kIbOneLaunchTiles) {
+        // few tiles: one launch, each block repeats its body's node update
+        if (advance)
+            k_ib_step<true><<<ntiles, 256, 0, st>>>(sims, bodies, blk, cur, d_t, d_status);
+        else
+            k_ib_step<false><<<ntiles, 256, 0, st>>>(sims, bodies, blk, cur, d_t, d_status);
+    } else {
+        if (advance)
+            k_ib_nodes<true><<<nbodies, 256, 0, st>>>(sims, bodies, cur, d_t, d_status);
+        else
+            k_ib_nodes<false><<<nbodies, 256, 0, st>>>(sims, bodies, cur, d_t, d_status);
+        k_ib_spread<<<ntiles, 256, 0, st>>>(bodies, blk, advance ? (cur ^ 1) : cur, d_status);
+    }
     return hipGetLastError();
 }
 

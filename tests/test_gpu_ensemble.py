@@ -51,3 +51,21 @@ def test_ensemble_member_matches_oracle():
         e = linf_rel(g[k], o[k])
         say(f"  {k} {e:.2e}")
         assert e <= 1e-4, k
+
+
+def test_body_update_paths_agree():
+    """Many patch tiles (here about a thousand) take the two-launch body update (nodes once, then
+    the spreading tiles); a single simulation takes the one-launch form in which every tile block
+    repeats its body's node update.  Both must give the same bits."""
+    sims = [wl.ensemble_member(i, sizes=(128,)) for i in range(48)]
+    say("case 48 sims 128x128, two-launch body update vs one-launch single runs, 40 steps")
+    ens = lb.Sim(sims, lb.make_options(seg_rows=16))
+    ens.step(40)
+    for i in (0, 23, 47):
+        one = lb.Sim([sims[i]], lb.make_options(seg_rows=16))
+        one.step(40)
+        a, b = ens.fields(i), one.fields(0)
+        for k in lb.FIELDS:
+            assert np.array_equal(a[k], b[k]), (i, k)
+        assert np.array_equal(ens.nodes(i)[0], one.nodes(0)[0]), i
+        one.close()
