@@ -86,12 +86,13 @@ class Surrogate:
         for i, net in enumerate(self.nets):
             net.set_params(mlp.init_params(widths, seed + 1000 * i))
         self.scale = 1.0
+        self.factor = 1.0
         self.threshold = 0.02
 
     def _t(self, a):
         return self.torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=self.device)
 
-    def fit(self, X, Y, epochs: int = 1800, batch: int = 256, lr: float = 2e-3, lr_min: float = 2e-5,
+    def fit(self, X, Y, epochs: int = 3600, batch: int = 256, lr: float = 2e-3, lr_min: float = 2e-5,
             seed: int = 0, log=None):
         """Adam with cosine learning-rate decay on the mean squared relative error of each series.
         The members train concurrently, each on its own stream and its own shuffling of the data."""
@@ -133,19 +134,16 @@ class Surrogate:
         spread = np.linalg.norm(outs.std(axis=0), axis=1) / np.maximum(np.linalg.norm(mean, axis=1), 1e-300)
         return mean, spread
 
-    def calibrate(self, X, Y, target: float = 0.02, quantile: float = 1.0):
-        """Largest threshold on the spread whose accepted validation rows keep the given quantile
-        (default: all of them) of their true relative error at or below target (0 when none does:
-        then every row is simulated)."""
+    def calibrate(self, X, Y, target: float = 0.02, coverage: float = 0.95):
+        """Error estimate = c * spread, with c the `coverage` quantile over validation rows of
+        (true relative error) / spread, so the estimate bounds the error on that share of them.
+        A row falls back to the LB when its estimate exceeds `target`; returns the spread
+        threshold target / c."""
         mean, spread = self.predict(X)
         err = np.linalg.norm(mean - Y, axis=1) / np.linalg.norm(Y, axis=1)
-        best = 0.0
-        for th in np.sort(spread):
-            acc = spread <= th
-            if acc.sum() >= 5 and np.quantile(err[acc], quantile) <= target:
-                best = float(th)
-        self.threshold = best
-        return best
+        self.factor = float(np.quantile(err / np.maximum(spread, 1e-30), coverage))
+        self.threshold = target / self.factor
+        return self.threshold
 
     def predict_with_fallback(self, seeds, X=None, batch: int = 512, **sim_kw):
         """Surrogate rows where the spread is at most the threshold; LB for the rest."""
@@ -165,7 +163,7 @@ class Surrogate:
         return out, dict(fallback=fb, t_inference=t_inf, t_fallback=t_lb, spread=spread)
 
 
-def study(train: int = 4096, test: int = 512, val: int = 512, members: int = 4, epochs: int = 1800,
+def study(train: int = 4096, test: int = 512, val: int = 512, members: int = 4, epochs: int = 3600,
           batch: int = 256, lr: float = 2e-3, sim_batch: int = 1024, target: float = 0.02, data=None, log=None):
     """Full surrogate study: `train` LB runs (seeds 3000 on; the last `val` held back to calibrate
     the threshold), `test` held-out runs (seeds 9000 on) for the error and the speedup
@@ -187,7 +185,7 @@ def study(train: int = 4096, test: int = 512, val: int = 512, members: int = 4, 
     t_fit = s.fit(X[:ntr], Y[:ntr], epochs=epochs, batch=batch, lr=lr, log=log)
     th = s.calibrate(X[ntr:], Y[ntr:], target=target)
     if log:
-        log(f"surrogate: threshold {th:.4g} on the spread")
+        log(f"surrogate: error estimate = {s.factor:.3g} x spread; LB when the spread exceeds {th:.4g}")
 
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -207,7 +205,8 @@ def study(train: int = 4096, test: int = 512, val: int = 512, members: int = 4, 
     return dict(
         observable="area-weighted restoring force along the pull, 64 samples", target_rel_l2=target,
         train_runs=train, held_out_runs=test, members=members, widths=s.widths,
-        t_lb_data_s=round(t_data, 3), t_fit_s=round(t_fit, 3), threshold=round(th, 6),
+        t_lb_data_s=round(t_data, 3), t_fit_s=round(t_fit, 3), estimate_factor=round(s.factor, 4),
+        spread_threshold=round(th, 6),
         t_lb_all_s=round(t_lb, 4), t_inference_s=round(info["t_inference"], 5),
         t_fallback_s=round(info["t_fallback"], 4), n_fallback=int(info["fallback"].size),
         speedup=round(t_lb / t_sur, 2), err_with_fallback=stats(err), err_network_only=stats(err_nn))
@@ -223,7 +222,7 @@ def main(argv=None):
     ap.add_argument("--test", type=int, default=512)
     ap.add_argument("--val", type=int, default=512)
     ap.add_argument("--members", type=int, default=4)
-    ap.add_argument("--epochs", type=int, default=1800)
+    ap.add_argument("--epochs", type=int, default=3600)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--sim-batch", type=int, default=1024)

@@ -160,3 +160,32 @@ def test_surrogate_pipeline_small():
     assert 0 < fb.size < len(test)
     _, Yt = sg.simulate(test, batch=16, **kw)
     assert np.array_equal(out[fb], Yt[fb])
+
+
+def test_surrogate_gains_over_lb():
+    """What the trained network buys, at reduced training size (512 LB runs of the full 128^2,
+    4096-step protocol; 64 held-out runs): its restoring-force series are within a few per cent
+    of the LB's (median <= 2%, 90th percentile <= 4%), and predicting them costs a small
+    fraction of simulating them."""
+    import time
+
+    import torch
+    from paper_2209_14889_amd import surrogate as sg
+    inp, Y = sg.simulate(range(3000, 3512), batch=512)
+    s = sg.Surrogate(members=2, max_batch=128)
+    s.fit(sg.features(inp), Y, epochs=800, batch=128)
+    test = list(range(9000, 9064))
+    Xt = sg.features([sg.wl.surrogate_inputs(x) for x in test])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, Yt = sg.simulate(test, batch=64)
+    t_lb = time.perf_counter() - t0
+    s.predict(Xt)
+    t0 = time.perf_counter()
+    mean, _ = s.predict(Xt)
+    t_inf = time.perf_counter() - t0
+    err = np.linalg.norm(mean - Yt, axis=1) / np.linalg.norm(Yt, axis=1)
+    print(f"median error {np.median(err):.4f}, p90 {np.quantile(err, 0.9):.4f}, LB {t_lb:.3f} s, "
+          f"network {t_inf * 1e3:.2f} ms", flush=True)
+    assert np.median(err) <= 0.02 and np.quantile(err, 0.9) <= 0.04
+    assert t_lb > 20 * t_inf
