@@ -250,6 +250,8 @@ int validate(const lb_sim_params *sims, int n_sims, const Opt &o) {
         if (!(p.D_p >= 0.0) || !(8.0 * p.D_p < 2.0)) return fail(LB_EINVAL, "sim %d: need 0 <= D_p and 8 D_p < 2", s);
         if (!(p.eta_p > 0.0)) return fail(LB_EINVAL, "sim %d: eta_p must be positive", s);
         if (!(p.P_clamp > 0.0 && p.P_clamp < 1.0)) return fail(LB_EINVAL, "sim %d: P_clamp must be in (0, 1)", s);
+        if (p.walls != 0 && p.walls != 1) return fail(LB_EINVAL, "sim %d: walls must be 0 or 1", s);
+        if (!std::isfinite(p.gx) || !std::isfinite(p.gy)) return fail(LB_EINVAL, "sim %d: gx, gy must be finite", s);
         if (p.n_bodies < 0 || p.n_bodies > kMaxBodies) return fail(LB_EINVAL, "sim %d: n_bodies out of range", s);
         if (p.n_bodies > 0 && !p.bodies) return fail(LB_EINVAL, "sim %d: bodies is NULL", s);
         for (int b = 0; b < p.n_bodies; ++b) {
@@ -262,6 +264,20 @@ int validate(const lb_sim_params *sims, int n_sims, const Opt &o) {
             if (2 * (int)std::ceil(ext) + 8 > lim)
                 return fail(LB_EINVAL, "sim %d body %d: body too large for the lattice", s, b);
             (void)ps;
+            if (p.walls) {
+                // every node's kernel footprint (rows floor(y) - 1 .. floor(y) + 2) inside the walls,
+                // with one row to spare for the predicted position
+                double lo = d.cy - ext, hi = d.cy + ext;
+                if (d.nodes) {
+                    lo = hi = d.nodes[1];
+                    for (int a = 0; a < d.n_nodes; ++a) {
+                        lo = std::min(lo, d.nodes[2 * a + 1]);
+                        hi = std::max(hi, d.nodes[2 * a + 1]);
+                    }
+                }
+                if (std::floor(lo) - 2 < 0 || std::floor(hi) + 3 > p.ny - 1)
+                    return fail(LB_EINVAL, "sim %d body %d: a node's kernel footprint reaches a wall", s, b);
+            }
         }
     }
     return LB_OK;
@@ -421,6 +437,7 @@ struct lb_handle {
     int fused_grid = 0;
     int fused_T = 256;
     int fused_seg = 0;
+    bool any_walls = false;   // some simulation has walls: launch the fused variant that handles them
     int n_items = 0;
     float tuned_ms = 0.f;
     // graph replay
@@ -445,6 +462,7 @@ int check_status(lb_handle *h) {
     HIPCHK(hipStreamSynchronize(h->stream));
     if (st & kStatusUnstable) return fail(LB_EUNSTABLE, "watchdog: non-finite or drifting mass");
     if (st & kStatusPatch) return fail(LB_ERANGE, "a body outgrew its force patch (node motion too large)");
+    if (st & kStatusWall) return fail(LB_ERANGE, "a node's kernel footprint reached a wall");
     return LB_OK;
 }
 
@@ -493,7 +511,7 @@ int launch_step(lb_handle *h, bool timed) {
         HIPCHK(hipEventRecord(a, h->stream));
     }
     if (h->opt.kernel == 0) {
-        HIPCHK(launch_fused(h->fused_T, fp16, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
+        HIPCHK(launch_fused(h->fused_T, fp16, h->any_walls, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
                             h->n_items, h->cur, h->d_t));
     } else {
         HIPCHK(launch_multipass(fp16, (int)h->plan.site_blk.size(), h->stream, h->d_sims, h->d_bodies, h->d_site,
@@ -560,7 +578,7 @@ int choose_fused_config(lb_handle *h) {
     };
     if (!h->opt.autotune) {
         int T = model_T();
-        int seg = h->opt.seg ? h->opt.seg : model_seg(h->plan.sims, T, cus * fused_blocks_per_cu(T, fp16));
+        int seg = h->opt.seg ? h->opt.seg : model_seg(h->plan.sims, T, cus * fused_blocks_per_cu(T, fp16, h->any_walls));
         return upload_items(h, T, seg, h->opt.grid);
     }
     struct Cand {
@@ -570,7 +588,7 @@ int choose_fused_config(lb_handle *h) {
     std::vector<Cand> cand;
     for (int T : {128, 256}) {
         if (h->opt.threads && T != h->opt.threads) continue;
-        int slots = cus * fused_blocks_per_cu(T, fp16);
+        int slots = cus * fused_blocks_per_cu(T, fp16, h->any_walls);
         int m = model_seg(h->plan.sims, T, slots);
         for (int seg : {m, std::max(4, m / 2), m * 2, m + 4, std::max(4, m - 4), 64}) {
             for (int grid : {0, (slots / 8) * 8}) {
@@ -590,7 +608,7 @@ int choose_fused_config(lb_handle *h) {
         int rc = upload_items(h, cand.front().T, cand.front().seg, cand.front().grid);
         if (rc) return rc;
         for (int r = 0; r < 30; ++r)
-            HIPCHK(launch_fused(cand.front().T, fp16, h->fused_grid, h->stream, h->d_sims, h->d_bodies,
+            HIPCHK(launch_fused(cand.front().T, fp16, h->any_walls, h->fused_grid, h->stream, h->d_sims, h->d_bodies,
                                 h->d_items, h->n_items, h->cur, h->d_t));
     }
     std::vector<float> tbest(cand.size(), 1e30f);
@@ -599,11 +617,11 @@ int choose_fused_config(lb_handle *h) {
             const Cand c = cand[ci];
             int rc = upload_items(h, c.T, c.seg, c.grid);
             if (rc) return rc;
-            HIPCHK(launch_fused(c.T, fp16, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
+            HIPCHK(launch_fused(c.T, fp16, h->any_walls, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
                                 h->n_items, h->cur, h->d_t));
             HIPCHK(hipEventRecord(e0, h->stream));
             for (int r = 0; r < 8; ++r)
-                HIPCHK(launch_fused(c.T, fp16, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
+                HIPCHK(launch_fused(c.T, fp16, h->any_walls, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
                                     h->n_items, h->cur, h->d_t));
             HIPCHK(hipEventRecord(e1, h->stream));
             HIPCHK(hipEventSynchronize(e1));
@@ -694,6 +712,7 @@ static int create_impl(const lb_sim_params *sims, int n_sims, const lb_options *
     if (rc) return rc;
     std::unique_ptr<lb_handle> h(new lb_handle());
     h->n_sims = n_sims;
+    for (int s = 0; s < n_sims; ++s) h->any_walls = h->any_walls || sims[s].walls != 0;
     h->opt = o;
     h->plan = make_plan(sims, n_sims, o);
     if (arena_bytes < h->plan.bytes)
@@ -765,6 +784,9 @@ static int create_impl(const lb_sim_params *sims, int n_sims, const lb_options *
         d.scale = scale;
         d.inv_scale = 1.0f / scale;
         d.ericksen = p.ericksen ? 1 : 0;
+        d.walls = p.walls;
+        d.gx = (float)p.gx;
+        d.gy = (float)p.gy;
         d.tab = A.ptr<float>(pl.oTab[sp.tab]);
         d.h[0] = A.ptr<void>(sp.oH0);
         d.h[1] = A.ptr<void>(sp.oH1);
@@ -913,6 +935,7 @@ int lb_step(lb_handle *h, int32_t n_steps) {
             h->wd_pending = false;
             if (*h->h_status & kStatusUnstable) return fail(LB_EUNSTABLE, "watchdog: non-finite or drifting mass");
             if (*h->h_status & kStatusPatch) return fail(LB_ERANGE, "a body outgrew its force patch");
+            if (*h->h_status & kStatusWall) return fail(LB_ERANGE, "a node's kernel footprint reached a wall");
         }
         const bool use_graph = h->opt.chunk > 0 && !h->opt.timing;
         int done = 0;

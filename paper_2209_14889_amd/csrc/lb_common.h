@@ -19,6 +19,7 @@ constexpr int kDefaultShift = 10;   // FP16 storage: offsets scaled by 2^10
 // status bits raised by kernels, read by the host at synchronising calls
 constexpr int kStatusPatch = 1;     // a body outgrew its force/velocity patch
 constexpr int kStatusUnstable = 2;  // watchdog: non-finite or drifting mass
+constexpr int kStatusWall = 4;      // a node's kernel footprint reached a wall
 
 struct SimDev {
     int nx, ny;
@@ -33,7 +34,8 @@ struct SimDev {
     float A2max, A4max;             // a2/s and a4/s^2 at smax
     float inv_scale, scale;         // FP16 storage scale 2^-S and 2^S (1 for FP32)
     int ericksen;
-    int pad0;
+    int walls;                      // 1: bounce-back walls below row 0 and above row ny-1
+    float gx, gy;                   // uniform body force
     const float *tab;               // per segment 8 floats: cubics in the local coordinate of A2 = a2/s, A4 = a4/s^2
     void *h[2];                     // post-collision population offsets, 9 planes (float or half)
     float *sig[2];                  // polymer stress planes sxx, syy, sxy

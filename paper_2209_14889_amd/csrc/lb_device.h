@@ -22,6 +22,7 @@ template <typename T> __device__ __forceinline__ LBK_GLOBAL T *gptr(T *p) { retu
 // D2Q9: rest, +x, +y, -x, -y, (+,+), (-,+), (-,-), (+,-)
 __device__ constexpr int kCX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __device__ constexpr int kCY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};   // c_kOpp[n] = -c_n
 __device__ constexpr float kW[9] = {4.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f,
                                     1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
 

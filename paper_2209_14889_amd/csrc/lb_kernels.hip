@@ -134,6 +134,7 @@ __global__ __launch_bounds__(256) void k_ib_nodes(const SimDev *__restrict__ sim
     const int n = B.n;
     const int dst = ADVANCE ? (cur ^ 1) : cur;
     bool bad = false;
+    bool wall = false;   // a node's kernel footprint reaches a wall
 
     const double2 *Rc = reinterpret_cast<const double2 *>(B.R[cur]);
     int ox = 0, oy = 0;
@@ -166,6 +167,7 @@ __global__ __launch_bounds__(256) void k_ib_nodes(const SimDev *__restrict__ sim
         float wx[4], wy[4];
         phi4(R.x, ix, wx);
         phi4(R.y, iy, wy);
+        if (S.walls && (iy < 1 || iy + 4 >= S.ny)) wall = true;   // one row of margin for the predictor position
         B.nix[2 * a] = ix;
         B.nix[2 * a + 1] = iy;
         float4 *w = reinterpret_cast<float4 *>(B.nw) + 2 * a;
@@ -202,6 +204,7 @@ __global__ __launch_bounds__(256) void k_ib_nodes(const SimDev *__restrict__ sim
         B.origin[4 * dst + 3] = wrapi(noy, S.ny);
     }
     if (bad) atomicOr(d_status, kStatusPatch);
+    if (wall) atomicOr(d_status, kStatusWall);
 }
 
 // One block per (body, 16x16 tile of its patch): f_IB(r) = sum_a f_a phi phi (App. A) as a gather
@@ -308,6 +311,7 @@ __global__ __launch_bounds__(256) void k_ib_step(const SimDev *__restrict__ sims
     const bool lead = bt.y == 0;
     bool bad = false;        // node outside its patch (every block finds the same; tile 0 reports)
     bool overflow = false;   // more footprints reach this tile than it can list
+    bool wall = false;       // a node's kernel footprint reaches a wall
 
     const double2 *Rc = reinterpret_cast<const double2 *>(B.R[cur]);
     int ox = 0, oy = 0;
@@ -380,6 +384,7 @@ __global__ __launch_bounds__(256) void k_ib_step(const SimDev *__restrict__ sims
             const double2 R = sR[a];
             phi4(R.x, ix, wx);
             phi4(R.y, iy, wy);
+            if (S.walls && (iy < 1 || iy + 4 >= S.ny)) wall = true;   // one row of margin for the predictor position
             flag = ix > X0 - 4 && ix < X0 + kPatchTile && iy > Y0 - 4 && iy < Y0 + kPatchTile;
         }
         const unsigned long long m = __ballot(flag);
@@ -424,6 +429,7 @@ __global__ __launch_bounds__(256) void k_ib_step(const SimDev *__restrict__ sims
         B.fib[(unsigned)(B.ps * B.ps) + i] = (float)fy;
     }
     if ((bad && lead) || overflow) atomicOr(d_status, kStatusPatch);
+    if (wall && lead) atomicOr(d_status, kStatusWall);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -440,7 +446,7 @@ __device__ __forceinline__ int xcd_remap(int v, int n) {
 
 __device__ __forceinline__ void inc_row(unsigned &r, unsigned ny) { r = (r + 1u == ny) ? 0u : r + 1u; }
 
-template <int T, typename HT>
+template <int T, typename HT, bool WALLS>
 __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, const BodyDev *__restrict__ bodies,
                                              const WorkItem *__restrict__ items, int n_items, int cur,
                                              int *__restrict__ d_t) {
@@ -510,7 +516,10 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
         const int f0 = wi.y0 - 4;
         unsigned rp1 = (unsigned)wrapi(f0 + 1, (int)ny), r0 = (unsigned)wrapi(f0, (int)ny);
         unsigned rm1 = (unsigned)wrapi(f0 - 1, (int)ny), rm2 = (unsigned)wrapi(f0 - 2, (int)ny);
-        unsigned rm4 = (unsigned)wrapi(f0 - 4, (int)ny);
+        unsigned rm3 = (unsigned)wrapi(f0 - 3, (int)ny), rm4 = (unsigned)wrapi(f0 - 4, (int)ny);
+        // walls: the rows next to them, whose neighbour beyond is a ghost
+        const bool walls = WALLS && S.walls != 0;   // the periodic variant has no wall code
+        const unsigned ytop = ny - 1u;
 
         // Loads for the next iteration, issued one iteration ahead.  Every lane loads (all
         // indices are wrapped into the lattice); lanes outside a stage's columns never use them.
@@ -573,15 +582,19 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                 pout.S2 = ld32(sgi, 2u * N + iS);
                 if (j + 1 >= 4) {
                     const unsigned yc = rm1 * nx, ym = rm2 * nx, yp = r0 * nx;
-                    pout.H[0] = Pop<HT>::ld_raw(hin, yc + x);
+                    // halfway bounce-back: what would come from beyond a wall is the opposite
+                    // direction's post-collision value at the same site
+                    const bool blo = walls && rm1 == 0u, bhi = walls && rm1 == ytop;
+                    const unsigned own = yc + x;
+                    pout.H[0] = Pop<HT>::ld_raw(hin, own);
                     pout.H[1] = Pop<HT>::ld_raw(hin, N + yc + xm);
-                    pout.H[2] = Pop<HT>::ld_raw(hin, 2u * N + ym + x);
+                    pout.H[2] = Pop<HT>::ld_raw(hin, blo ? 4u * N + own : 2u * N + ym + x);
                     pout.H[3] = Pop<HT>::ld_raw(hin, 3u * N + yc + xp);
-                    pout.H[4] = Pop<HT>::ld_raw(hin, 4u * N + yp + x);
-                    pout.H[5] = Pop<HT>::ld_raw(hin, 5u * N + ym + xm);
-                    pout.H[6] = Pop<HT>::ld_raw(hin, 6u * N + ym + xp);
-                    pout.H[7] = Pop<HT>::ld_raw(hin, 7u * N + yp + xp);
-                    pout.H[8] = Pop<HT>::ld_raw(hin, 8u * N + yp + xm);
+                    pout.H[4] = Pop<HT>::ld_raw(hin, bhi ? 2u * N + own : 4u * N + yp + x);
+                    pout.H[5] = Pop<HT>::ld_raw(hin, blo ? 7u * N + own : 5u * N + ym + xm);
+                    pout.H[6] = Pop<HT>::ld_raw(hin, blo ? 8u * N + own : 6u * N + ym + xp);
+                    pout.H[7] = Pop<HT>::ld_raw(hin, bhi ? 5u * N + own : 7u * N + yp + xp);
+                    pout.H[8] = Pop<HT>::ld_raw(hin, bhi ? 6u * N + own : 8u * N + yp + xm);
                 }
             }
             __syncthreads();
@@ -592,11 +605,12 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             exy2 = exy1;
             eyy2 = eyy1;
             if (j >= 2 && colB) {
+                const int an = walls && rm1 == ytop ? a1 : a0, as = walls && rm1 == 0u ? a1 : a2;
                 double Pc[2] = {rP[a1][0][tid], rP[a1][1][tid]};
                 double Pe[2] = {rP[a1][0][tid + 1], rP[a1][1][tid + 1]};
                 double Pw[2] = {rP[a1][0][tid - 1], rP[a1][1][tid - 1]};
-                double Pn[2] = {rP[a0][0][tid], rP[a0][1][tid]};
-                double Ps[2] = {rP[a2][0][tid], rP[a2][1][tid]};
+                double Pn[2] = {rP[an][0][tid], rP[an][1][tid]};
+                double Ps[2] = {rP[as][0][tid], rP[as][1][tid]};
                 float E[4];
                 ericksen(S, Pc, Pe, Pw, Pn, Ps, E);
                 rE[o1][0][tid] = E[0];
@@ -608,12 +622,18 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
 
             // ---- stage C: force, moments, collision at row f-2
             if (j >= 4 && colC) {
-                float Fx = 0.5f * (rS[b2][0][tid + 1] - rS[b2][0][tid - 1]) + 0.5f * (rS[b1][2][tid] - rS[b3][2][tid]);
-                float Fy = 0.5f * (rS[b2][2][tid + 1] - rS[b2][2][tid - 1]) + 0.5f * (rS[b1][1][tid] - rS[b3][1][tid]);
+                const bool clo = walls && rm2 == 0u, chi = walls && rm2 == ytop;
+                const int bn = chi ? b2 : b1, bs = clo ? b2 : b3;
+                float Fx = 0.5f * (rS[b2][0][tid + 1] - rS[b2][0][tid - 1]) + 0.5f * (rS[bn][2][tid] - rS[bs][2][tid]);
+                float Fy = 0.5f * (rS[b2][2][tid + 1] - rS[b2][2][tid - 1]) + 0.5f * (rS[bn][1][tid] - rS[bs][1][tid]);
                 if (S.ericksen) {
-                    Fx += 0.5f * (rE[o0][0][tid + 1] - rE[o0][0][tid - 1]) + 0.5f * (exy1 - exy3);
-                    Fy += 0.5f * (rE[o0][1][tid + 1] - rE[o0][1][tid - 1]) + 0.5f * (eyy1 - eyy3);
+                    const float exn = chi ? exy2 : exy1, exs = clo ? exy2 : exy3;
+                    const float eyn = chi ? eyy2 : eyy1, eys = clo ? eyy2 : eyy3;
+                    Fx += 0.5f * (rE[o0][0][tid + 1] - rE[o0][0][tid - 1]) + 0.5f * (exn - exs);
+                    Fy += 0.5f * (rE[o0][1][tid + 1] - rE[o0][1][tid - 1]) + 0.5f * (eyn - eys);
                 }
+                Fx += S.gx;
+                Fy += S.gy;
                 if (nib > 0)
                     ib_force_list(sIB, nib, (int)nx, (int)ny, (int)x, (int)rm2, Fx, Fy);
                 else if (nib < 0)
@@ -644,21 +664,27 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
 #pragma unroll
                 for (int q = 0; q < 3; ++q) X[q] = rS[b3][q][tid];
                 if (j >= 6) {
-                    cout.g = grad_v(rV[o1][0][tid + 1], rV[o1][0][tid - 1], rV[o0][0][tid], cin.vx,
-                                    rV[o1][1][tid + 1], rV[o1][1][tid - 1], rV[o0][1][tid], cin.vy);
+                    // walls: mirror ghosts for sigma and P, no-slip (negated) ghosts for v
+                    const bool dlo = walls && rm3 == 0u, dhi = walls && rm3 == ytop;
+                    const float vxn = dhi ? -cout.vx : rV[o0][0][tid], vyn = dhi ? -cout.vy : rV[o0][1][tid];
+                    const float vxs = dlo ? -cout.vx : cin.vx, vys = dlo ? -cout.vy : cin.vy;
+                    cout.g = grad_v(rV[o1][0][tid + 1], rV[o1][0][tid - 1], vxn, vxs,
+                                    rV[o1][1][tid + 1], rV[o1][1][tid - 1], vyn, vys);
                     double Pe[2] = {rP[a3][0][tid + 1], rP[a3][1][tid + 1]};
                     double Pw[2] = {rP[a3][0][tid - 1], rP[a3][1][tid - 1]};
-                    double Pn[2] = {rP[a2][0][tid], rP[a2][1][tid]};
-                    double Ps[2] = {cin.p0, cin.p1};
+                    const int an = dhi ? a3 : a2;
+                    double Pn[2] = {rP[an][0][tid], rP[an][1][tid]};
+                    double Ps[2] = {dlo ? Pc[0] : cin.p0, dlo ? Pc[1] : cin.p1};
                     cout.k = stiffness(S, sTab, (float)Pc[0], (float)Pc[1]);
                     float Xe[3], Xw[3], Xn[3], Rs[3];
+                    const int bn = dhi ? b3 : b2;
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
                         Xe[q] = rS[b3][q][tid + 1];
                         Xw[q] = rS[b3][q][tid - 1];
-                        Xn[q] = rS[b2][q][tid];
+                        Xn[q] = rS[bn][q][tid];
                     }
-                    const float Xs[3] = {cin.s0, cin.s1, cin.s2};
+                    const float Xs[3] = {dlo ? X[0] : cin.s0, dlo ? X[1] : cin.s1, dlo ? X[2] : cin.s2};
                     rhs_sigma(S, cout.k, cout.g, cout.vx, cout.vy, X, Xe, Xw, Xn, Xs, Rs);
                     double Rp[2];
                     rhs_P(S, cout.g, cout.vx, cout.vy, Pc, Pe, Pw, Pn, Ps, Rp);
@@ -686,21 +712,23 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                 Y[0] = rQp[o0][0][tid];
                 Y[1] = rQp[o0][1][tid];
                 if (j >= 8) {
+                    const bool elo = walls && rm4 == 0u, ehi = walls && rm4 == ytop;
+                    const int on = ehi ? o0 : o1;
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
                         Xe[q] = rQs[o0][q][tid + 1];
                         Xw[q] = rQs[o0][q][tid - 1];
-                        Xn[q] = rQs[o1][q][tid];
+                        Xn[q] = rQs[on][q][tid];
                     }
-                    const float Xs[3] = {cin.q0, cin.q1, cin.q2};
+                    const float Xs[3] = {elo ? X[0] : cin.q0, elo ? X[1] : cin.q1, elo ? X[2] : cin.q2};
                     rhs_sigma(S, cin.k, cin.g, cin.vx, cin.vy, X, Xe, Xw, Xn, Xs, Rs);
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
                         Ye[q] = rQp[o0][q][tid + 1];
                         Yw[q] = rQp[o0][q][tid - 1];
-                        Yn[q] = rQp[o1][q][tid];
+                        Yn[q] = rQp[on][q][tid];
                     }
-                    const double Ys[2] = {cin.qp0, cin.qp1};
+                    const double Ys[2] = {elo ? Y[0] : cin.qp0, elo ? Y[1] : cin.qp1};
                     rhs_P(S, cin.g, cin.vx, cin.vy, Y, Ye, Yw, Yn, Ys, Rp);
                     const unsigned o = rm4 * nx + x;
                     st32(sgo, o, 0.5f * ((cin.s0 + X[0]) + Rs[0]));
@@ -719,6 +747,7 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             inc_row(r0, ny);
             inc_row(rm1, ny);
             inc_row(rm2, ny);
+            inc_row(rm3, ny);
             inc_row(rm4, ny);
         };
 
@@ -734,17 +763,22 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
 // multi-pass reference step: one thread per site, intermediate fields in scratch planes
 // ------------------------------------------------------------------------------------------------
 
+// site indices of (x, y) and its four neighbours; with walls the row beyond a wall is the mirror
+// ghost (the site itself: zero normal derivative), flagged in lo / hi for odd (no-slip) fields
 struct Nb {
     size_t c, e, w, n, s;
+    bool lo, hi;
 };
-__device__ __forceinline__ Nb nbrs(int x, int y, int nx, int ny) {
+__device__ __forceinline__ Nb nbrs(int x, int y, int nx, int ny, int walls = 0) {
     Nb q;
     size_t row = (size_t)y * nx;
     q.c = row + x;
     q.e = row + wrapi(x + 1, nx);
     q.w = row + wrapi(x - 1, nx);
-    q.n = (size_t)wrapi(y + 1, ny) * nx + x;
-    q.s = (size_t)wrapi(y - 1, ny) * nx + x;
+    q.lo = walls && y == 0;
+    q.hi = walls && y == ny - 1;
+    q.n = q.hi ? q.c : (size_t)wrapi(y + 1, ny) * nx + x;
+    q.s = q.lo ? q.c : (size_t)wrapi(y - 1, ny) * nx + x;
     return q;
 }
 
@@ -767,7 +801,7 @@ __global__ __launch_bounds__(256) void k_mp_sigE(const SimDev *__restrict__ sims
     const SimDev &S = sims[sim];
     const size_t N = (size_t)S.nx * S.ny;
     const double *P = S.P[cur];
-    Nb q = nbrs(x, y, S.nx, S.ny);
+    Nb q = nbrs(x, y, S.nx, S.ny, S.walls);
     double Pc[2] = {P[q.c], P[N + q.c]}, Pe[2] = {P[q.e], P[N + q.e]}, Pw[2] = {P[q.w], P[N + q.w]};
     double Pn[2] = {P[q.n], P[N + q.n]}, Ps[2] = {P[q.s], P[N + q.s]};
     float E[4];
@@ -782,8 +816,8 @@ __device__ __forceinline__ void site_force(const SimDev &S, const BodyDev *bodie
     const float *sg = S.sig[cur];
     fpx = 0.5f * (sg[q.e] - sg[q.w]) + 0.5f * (sg[2 * N + q.n] - sg[2 * N + q.s]);
     fpy = 0.5f * (sg[2 * N + q.e] - sg[2 * N + q.w]) + 0.5f * (sg[N + q.n] - sg[N + q.s]);
-    Fx = fpx;
-    Fy = fpy;
+    Fx = fpx + S.gx;
+    Fy = fpy + S.gy;
     if (S.ericksen) {
         const float *E = S.sE;
         Fx += 0.5f * (E[q.e] - E[q.w]) + 0.5f * (E[N + q.n] - E[N + q.s]);
@@ -797,7 +831,12 @@ __device__ __forceinline__ void pull_pops(const SimDev &S, const HT *hin, int x,
     const size_t N = (size_t)S.nx * S.ny;
 #pragma unroll
     for (int n = 0; n < 9; ++n) {
-        size_t i = (size_t)wrapi(y - kCY[n], S.ny) * S.nx + wrapi(x - kCX[n], S.nx);
+        const int ys = y - kCY[n];
+        if (S.walls && (ys < 0 || ys >= S.ny)) {   // halfway bounce-back: the opposite direction
+            d[n] = Pop<HT>::load(hin, kOpp[n] * N + (size_t)y * S.nx + x, S.inv_scale);   // at this site
+            continue;
+        }
+        size_t i = (size_t)wrapi(ys, S.ny) * S.nx + wrapi(x - kCX[n], S.nx);
         d[n] = Pop<HT>::load(hin, n * N + i, S.inv_scale);
     }
 }
@@ -809,7 +848,7 @@ __global__ __launch_bounds__(256) void k_mp_lb(const SimDev *__restrict__ sims, 
     if (!site_of(blk, sims, sim, x, y)) return;
     const SimDev &S = sims[sim];
     const size_t N = (size_t)S.nx * S.ny;
-    Nb q = nbrs(x, y, S.nx, S.ny);
+    Nb q = nbrs(x, y, S.nx, S.ny, S.walls);
     float Fx, Fy, fpx, fpy;
     site_force(S, bodies, cur, x, y, q, Fx, Fy, fpx, fpy);
     float d[9];
@@ -826,7 +865,9 @@ __global__ __launch_bounds__(256) void k_mp_lb(const SimDev *__restrict__ sims, 
 __device__ __forceinline__ Grad grad_at(const SimDev &S, const Nb &q) {
     const size_t N = (size_t)S.nx * S.ny;
     const float *v = S.v;
-    return grad_v(v[q.e], v[q.w], v[q.n], v[q.s], v[N + q.e], v[N + q.w], v[N + q.n], v[N + q.s]);
+    // no-slip ghosts beyond a wall: the negated velocity of the wall row
+    const float sn = q.hi ? -1.0f : 1.0f, ss = q.lo ? -1.0f : 1.0f;
+    return grad_v(v[q.e], v[q.w], sn * v[q.n], ss * v[q.s], v[N + q.e], v[N + q.w], sn * v[N + q.n], ss * v[N + q.s]);
 }
 
 __device__ __forceinline__ void gather3(const float *f, size_t N, const Nb &q, float X[3], float Xe[3], float Xw[3],
@@ -856,7 +897,7 @@ __global__ __launch_bounds__(256) void k_mp_pred(const SimDev *__restrict__ sims
     if (!site_of(blk, sims, sim, x, y)) return;
     const SimDev &S = sims[sim];
     const size_t N = (size_t)S.nx * S.ny;
-    Nb q = nbrs(x, y, S.nx, S.ny);
+    Nb q = nbrs(x, y, S.nx, S.ny, S.walls);
     Grad g = grad_at(S, q);
     float ux = S.v[q.c], uy = S.v[N + q.c];
     float X[3], Xe[3], Xw[3], Xn[3], Xs[3], Rs[3];
@@ -876,7 +917,7 @@ __global__ __launch_bounds__(256) void k_mp_corr(const SimDev *__restrict__ sims
     if (!site_of(blk, sims, sim, x, y)) return;
     const SimDev &S = sims[sim];
     const size_t N = (size_t)S.nx * S.ny;
-    Nb q = nbrs(x, y, S.nx, S.ny);
+    Nb q = nbrs(x, y, S.nx, S.ny, S.walls);
     Grad g = grad_at(S, q);
     float ux = S.v[q.c], uy = S.v[N + q.c];
     const double *P = S.P[cur];
@@ -906,7 +947,7 @@ __global__ __launch_bounds__(256) void k_readout(const SimDev *__restrict__ sims
     if (!site_of(blk, sims, sim, x, y)) return;
     const SimDev &S = sims[sim];
     const size_t N = (size_t)S.nx * S.ny;
-    Nb q = nbrs(x, y, S.nx, S.ny);
+    Nb q = nbrs(x, y, S.nx, S.ny, S.walls);
     float Fx, Fy, fpx, fpy;
     site_force(S, bodies, cur, x, y, q, Fx, Fy, fpx, fpy);
     float d[9];
@@ -1077,7 +1118,7 @@ __global__ __launch_bounds__(256) void k_body_force(const SimDev *__restrict__ s
                 if ((ya > Y) != (yb > Y) && X < (xb - xa) * (Y - ya) / (yb - ya) + xa) in = !in;
             }
             if (!in) continue;
-            Nb q = nbrs(wrapi(X, S.nx), wrapi(Y, S.ny), S.nx, S.ny);
+            Nb q = nbrs(wrapi(X, S.nx), wrapi(Y, S.ny), S.nx, S.ny, S.walls);
             ax += divx(q);
             ay += divy(q);
         }
@@ -1095,7 +1136,7 @@ __global__ __launch_bounds__(256) void k_body_force(const SimDev *__restrict__ s
                 w += edge_box(sR[b].x, sR[b].y, sR[a].x, sR[a].y, X - 0.5, X + 0.5, Y - 0.5, Y + 0.5);
             w *= orient;
             if (w == 0.0) continue;
-            Nb q = nbrs(wrapi(X, S.nx), wrapi(Y, S.ny), S.nx, S.ny);
+            Nb q = nbrs(wrapi(X, S.nx), wrapi(Y, S.ny), S.nx, S.ny, S.walls);
             bx += w * divx(q);
             by += w * divy(q);
         }
@@ -1146,33 +1187,32 @@ hipError_t launch_ib(bool advance, int nbodies, int ntiles, hipStream_t st, cons
     return hipGetLastError();
 }
 
-hipError_t launch_fused(int T, bool fp16, int grid, hipStream_t st, const SimDev *sims, const BodyDev *bodies,
-                        const WorkItem *items, int n_items, int cur, int *d_t) {
+// the kernel for (work-group size, storage type, walls)
+typedef void (*FusedFn)(const SimDev *, const BodyDev *, const WorkItem *, int, int, int *);
+static FusedFn fused_fn(int T, bool fp16, bool walls) {
     if (T == 128) {
-        if (fp16)
-            k_fused<128, __half><<<grid, 128, 0, st>>>(sims, bodies, items, n_items, cur, d_t);
-        else
-            k_fused<128, float><<<grid, 128, 0, st>>>(sims, bodies, items, n_items, cur, d_t);
-    } else if (T == 256) {
-        if (fp16)
-            k_fused<256, __half><<<grid, 256, 0, st>>>(sims, bodies, items, n_items, cur, d_t);
-        else
-            k_fused<256, float><<<grid, 256, 0, st>>>(sims, bodies, items, n_items, cur, d_t);
-    } else {
-        return hipErrorInvalidValue;
+        if (fp16) return walls ? k_fused<128, __half, true> : k_fused<128, __half, false>;
+        return walls ? k_fused<128, float, true> : k_fused<128, float, false>;
     }
+    if (T == 256) {
+        if (fp16) return walls ? k_fused<256, __half, true> : k_fused<256, __half, false>;
+        return walls ? k_fused<256, float, true> : k_fused<256, float, false>;
+    }
+    return nullptr;
+}
+
+hipError_t launch_fused(int T, bool fp16, bool walls, int grid, hipStream_t st, const SimDev *sims,
+                        const BodyDev *bodies, const WorkItem *items, int n_items, int cur, int *d_t) {
+    FusedFn f = fused_fn(T, fp16, walls);
+    if (!f) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(f, dim3(grid), dim3(T), 0, st, sims, bodies, items, n_items, cur, d_t);
     return hipGetLastError();
 }
 
-int fused_blocks_per_cu(int T, bool fp16) {
+int fused_blocks_per_cu(int T, bool fp16, bool walls) {
+    FusedFn f = fused_fn(T, fp16, walls);
     int n = 0;
-    hipError_t e;
-    if (T == 128)
-        e = fp16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fused<128, __half>, 128, 0)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fused<128, float>, 128, 0);
-    else
-        e = fp16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fused<256, __half>, 256, 0)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fused<256, float>, 256, 0);
+    hipError_t e = f ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, T, 0) : hipErrorInvalidValue;
     return e == hipSuccess && n > 0 ? n : 1;
 }
 

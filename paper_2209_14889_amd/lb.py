@@ -41,7 +41,8 @@ class SimParams(ctypes.Structure):
         ("Kx", ctypes.c_double * 4), ("eta_p", ctypes.c_double), ("D_p", ctypes.c_double),
         ("xi", ctypes.c_double), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
         ("kappa", ctypes.c_double), ("Gamma", ctypes.c_double), ("P_clamp", ctypes.c_double),
-        ("ericksen", ctypes.c_int32), ("n_bodies", ctypes.c_int32),
+        ("ericksen", ctypes.c_int32), ("walls", ctypes.c_int32), ("gx", ctypes.c_double),
+        ("gy", ctypes.c_double), ("n_bodies", ctypes.c_int32),
         ("bodies", ctypes.POINTER(BodyDesc)),
         ("init_P", _dp), ("init_sigma", _dp), ("init_h", _dp),
     ]
@@ -137,6 +138,8 @@ class _Marshal:
         p.xi, p.alpha, p.beta, p.kappa, p.Gamma = q["xi"], q["alpha"], q["beta"], q["kappa"], q["Gamma"]
         p.P_clamp = q["P_clamp"]
         p.ericksen = int(q.get("ericksen", 1))
+        p.walls = int(q.get("walls", 0))
+        p.gx, p.gy = float(q.get("gx", 0.0)), float(q.get("gy", 0.0))
         bodies = (BodyDesc * max(1, len(s.bodies)))()
         for j, b in enumerate(s.bodies):
             d = BodyDesc()

@@ -13,7 +13,8 @@ def oracle_params(sim: "wl.SimSpec", **over) -> dict:
     p = sim.params
     d = dict(nx=sim.nx, ny=sim.ny, tau=p["tau"], Kx=p["Kx"], eta_p=p["eta_p"], D_p=p["D_p"],
              xi=p["xi"], alpha=p["alpha"], beta=p["beta"], kappa=p["kappa"], Gamma=p["Gamma"],
-             P_clamp=p["P_clamp"], ericksen=p["ericksen"])
+             P_clamp=p["P_clamp"], ericksen=p["ericksen"], walls=p.get("walls", 0), gx=p.get("gx", 0.0),
+             gy=p.get("gy", 0.0))
     d.update(over)
     return d
 

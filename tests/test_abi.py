@@ -81,3 +81,14 @@ def test_mlp_sizes_are_host_side():
     assert n.value > 4 * 4 * mlp.n_params(w)   # params, grads and two moments at least
     bad = mlp.make_config([5, 0, 64], 512)
     assert mlp.lib().lb_mlp_query_bytes(ctypes.byref(bad), ctypes.byref(n)) != lb.LB_OK
+
+
+def test_validation_rejects_bodies_at_walls():
+    spec = wl.small_case(3, 48, 40, walls=1).sims[0]
+    rc, _ = _query([spec])
+    assert rc == lb.LB_OK
+    spec.bodies[0].R[:, 1] -= spec.bodies[0].R[:, 1].min() - 1.5   # lowest node at y = 1.5
+    rc, _ = _query([spec])
+    assert rc != lb.LB_OK and "wall" in lb.lib().lb_last_error().decode()
+    spec.params["walls"] = 2
+    assert _query([spec])[0] != lb.LB_OK
