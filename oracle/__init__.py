@@ -45,6 +45,9 @@ class _Body(ctypes.Structure):
         ("n", ctypes.c_int), ("k_spring", ctypes.c_double), ("eps_angle", ctypes.c_double),
         ("l_eq", ctypes.c_double), ("pull_fx", ctypes.c_double), ("pull_fy", ctypes.c_double),
         ("t_on", ctypes.c_double), ("t_off", ctypes.c_double), ("width", ctypes.c_double),
+        ("trap_k", ctypes.c_double), ("trap_x0", ctypes.c_double), ("trap_y0", ctypes.c_double),
+        ("trap_dx", ctypes.c_double), ("trap_dy", ctypes.c_double), ("trap_t1", ctypes.c_double),
+        ("trap_t2", ctypes.c_double), ("trap_w", ctypes.c_double),
         ("R", ctypes.POINTER(ctypes.c_double)),
     ]
 
@@ -72,6 +75,11 @@ def lib():
         L.orc_pull_factor.restype = ctypes.c_double
         L.orc_pull_factor.argtypes = [ctypes.POINTER(_Body), ctypes.c_double]
         L.orc_body_energy.restype = ctypes.c_double
+        L.orc_trap_k.restype = ctypes.c_double
+        L.orc_trap_k.argtypes = [ctypes.POINTER(_Body), ctypes.c_double]
+        L.orc_trap_energy.restype = ctypes.c_double
+        L.orc_trap_energy.argtypes = [ctypes.POINTER(_Body), ctypes.c_double]
+        L.orc_trap_pos.argtypes = [ctypes.POINTER(_Body), ctypes.c_double, _dp]
         L.orc_body_energy.argtypes = [ctypes.POINTER(_Body)]
         L.orc_spread.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _dp, _dp, _dp, _dp]
         L.orc_interp.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, _dp, _dp, _dp, _dp]
@@ -167,6 +175,7 @@ class Body:
     t_on: float = 0.0             # logistic pull schedule (width 0: constant pull)
     t_off: float = 0.0
     width: float = 0.0
+    trap: dict | None = None      # k, x0, y0, dx, dy, t1, t2, w (harmonic trap, see orc_body)
     _c: _Body = field(default=None, repr=False)
 
     def cstruct(self) -> _Body:
@@ -176,6 +185,11 @@ class Body:
         b.k_spring, b.eps_angle, b.l_eq = self.k_spring, self.eps_angle, self.l_eq
         b.pull_fx, b.pull_fy = float(self.pull[0]), float(self.pull[1])
         b.t_on, b.t_off, b.width = float(self.t_on), float(self.t_off), float(self.width)
+        if self.trap:
+            tr = self.trap
+            b.trap_k, b.trap_x0, b.trap_y0 = float(tr["k"]), float(tr["x0"]), float(tr["y0"])
+            b.trap_dx, b.trap_dy = float(tr["dx"]), float(tr["dy"])
+            b.trap_t1, b.trap_t2, b.trap_w = float(tr["t1"]), float(tr["t2"]), float(tr["w"])
         b.R = self.R.ctypes.data_as(_dp)
         self._c = b
         return b
@@ -190,6 +204,17 @@ class Body:
 
     def energy(self) -> float:
         return lib().orc_body_energy(ctypes.byref(self.cstruct()))
+
+    def trap_k(self, t: float) -> float:
+        return lib().orc_trap_k(ctypes.byref(self.cstruct()), float(t))
+
+    def trap_pos(self, t: float) -> np.ndarray:
+        out = np.zeros(2)
+        lib().orc_trap_pos(ctypes.byref(self.cstruct()), float(t), _ptr(out))
+        return out
+
+    def trap_energy(self, t: float) -> float:
+        return lib().orc_trap_energy(ctypes.byref(self.cstruct()), float(t))
 
 
 class Sim:

@@ -203,6 +203,38 @@ double orc_pull_factor(const orc_body *b, double t) {
     return 1.0 / (1.0 + exp(-(t - b->t_on) / b->width)) - 1.0 / (1.0 + exp(-(t - b->t_off) / b->width));
 }
 
+static double logistic(double x) { return 1.0 / (1.0 + exp(-x)); }
+static double softplus(double x) { return x > 30.0 ? x + log1p(exp(-x)) : log1p(exp(x)); }
+
+double orc_trap_k(const orc_body *b, double t) {
+    if (b->trap_k == 0.0) return 0.0;
+    return b->trap_k * (logistic((t - b->trap_t1) / b->trap_w) - logistic((t - b->trap_t2) / b->trap_w));
+}
+
+void orc_trap_pos(const orc_body *b, double t, double out[2]) {
+    double w = b->trap_w, T = b->trap_t2 - b->trap_t1;
+    double rho = T > 0.0 ? (w / T) * (softplus((t - b->trap_t1) / w) - softplus((t - b->trap_t2) / w)) : 0.0;
+    out[0] = b->trap_x0 + b->trap_dx * rho;
+    out[1] = b->trap_y0 + b->trap_dy * rho;
+}
+
+static void centre_of_mass(const orc_body *b, double c[2]) {
+    c[0] = c[1] = 0.0;
+    for (int a = 0; a < b->n; ++a) {
+        c[0] += b->R[2 * a];
+        c[1] += b->R[2 * a + 1];
+    }
+    c[0] /= b->n;
+    c[1] /= b->n;
+}
+
+double orc_trap_energy(const orc_body *b, double t) {
+    double e[2], c[2];
+    orc_trap_pos(b, t, e);
+    centre_of_mass(b, c);
+    return 0.5 * orc_trap_k(b, t) * ((e[0] - c[0]) * (e[0] - c[0]) + (e[1] - c[1]) * (e[1] - c[1]));
+}
+
 void orc_node_forces(const orc_body *b, double t, double *f) {
     int n = b->n;
     const double *R = b->R;
@@ -242,6 +274,17 @@ void orc_node_forces(const orc_body *b, double t, double *f) {
     for (int a = 0; a < n; ++a) {
         f[2 * a] += s * b->pull_fx / n;
         f[2 * a + 1] += s * b->pull_fy / n;
+    }
+    /* trap: -d/dR_a of k/2 |R_ext - R_com|^2 = k (R_ext - R_com) / n on every node */
+    double k = orc_trap_k(b, t);
+    if (k != 0.0) {
+        double e[2], c[2];
+        orc_trap_pos(b, t, e);
+        centre_of_mass(b, c);
+        for (int a = 0; a < n; ++a) {
+            f[2 * a] += k * (e[0] - c[0]) / n;
+            f[2 * a + 1] += k * (e[1] - c[1]) / n;
+        }
     }
 }
 

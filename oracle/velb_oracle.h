@@ -44,6 +44,13 @@ typedef struct {
     double pull_fx, pull_fy;  /* total external force, shared equally by the nodes */
     double t_on, t_off, width;/* pull switched on/off by logistic functions of time (steps) of
                                  scale `width` centred at t_on and t_off; width <= 0: constant */
+    /* harmonic trap on the centre of mass (App. A, eqUtrap): u = k(t)/2 |R_ext(t) - R_com|^2 with
+     * k(t) = trap_k [S((t - t1)/w) - S((t - t2)/w)], S the logistic function, and
+     * R_ext(t) = (trap_x0, trap_y0) + (trap_dx, trap_dy) rho(t), where
+     * rho(t) = (w / (t2 - t1)) [sp((t - t1)/w) - sp((t - t2)/w)], sp(x) = ln(1 + e^x): the trap
+     * moves at constant speed from t1 to t2 with logistic starts and stops (the integral of the
+     * switching function) and lets go at t2.  trap_k = 0: no trap. */
+    double trap_k, trap_x0, trap_y0, trap_dx, trap_dy, trap_t1, trap_t2, trap_w;
     double *R;          /* 2n doubles, updated in place */
 } orc_body;
 
@@ -62,10 +69,14 @@ void orc_stiffness(double Px, double Py, const double Kx[4], double P_clamp, dou
 double orc_phi(double r);
 /* pull schedule factor at time t (1 when width <= 0) */
 double orc_pull_factor(const orc_body *b, double t);
-/* node forces -dU/dR (spring + bending) plus the pull share at time t; f has 2n entries */
+/* node forces -dU/dR (spring + bending + trap) plus the pull share at time t; f has 2n entries */
 void orc_node_forces(const orc_body *b, double t, double *f);
-/* total elastic energy of the loop (spring + bending), pull excluded */
+/* total elastic energy of the loop (spring + bending), pull and trap excluded */
 double orc_body_energy(const orc_body *b);
+/* trap stiffness k(t), trap position R_ext(t) (out[2]) and trap energy at time t */
+double orc_trap_k(const orc_body *b, double t);
+void orc_trap_pos(const orc_body *b, double t, double out[2]);
+double orc_trap_energy(const orc_body *b, double t);
 /* add sum_a f_a phi phi to the force planes fx, fy (ny*nx each) */
 void orc_spread(const orc_params *p, int n, const double *R, const double *f, double *fx, double *fy);
 /* interpolate the velocity planes ux, uy at n points R -> out (2n) */

@@ -196,3 +196,50 @@ def test_area_force_is_continuous_in_the_nodes_unlike_the_site_sum():
     # |div sigma|, the site sum jumps by whole sites
     assert da < 0.2 * ds
     assert da < 0.01 * 2 * math.pi * 6 * 4e-3
+
+
+# --- harmonic trap (App. A, eqUtrap) ---------------------------------------------------------
+
+TRAP = dict(k=0.02, x0=5.3, y0=6.1, dx=4.0, dy=-1.5, t1=120.0, t2=920.0, w=30.0)
+
+
+def test_trap_schedule_closed_forms():
+    b = oracle.Body(R=oracle.polygon(5.0, 6.0, 3.0, 12), trap=TRAP)
+    S = lambda x: 1.0 / (1.0 + math.exp(-x))
+    for t in (0.0, 120.0, 500.0, 920.0, 1500.0):
+        assert abs(b.trap_k(t) - 0.02 * (S((t - 120) / 30) - S((t - 920) / 30))) < 1e-16
+    # the trap position is the integral of the switching function: half way at the midpoint (by
+    # the symmetry sp(x) - sp(-x) = x), at rest before t1 and at the full pull after t2
+    mid = b.trap_pos(520.0)
+    assert np.max(np.abs(mid - [5.3 + 2.0, 6.1 - 0.75])) < 1e-12
+    assert np.max(np.abs(b.trap_pos(-2000.0) - [5.3, 6.1])) < 1e-12
+    assert np.max(np.abs(b.trap_pos(4000.0) - [9.3, 4.6])) < 1e-12
+    # its velocity is (d / (t2 - t1)) (S((t - t1)/w) - S((t - t2)/w)): the pull speed switched on
+    # and off with the stiffness
+    v = (b.trap_pos(521.0) - b.trap_pos(519.0)) / 2.0
+    vex = np.array([4.0, -1.5]) / 800.0 * (S(400 / 30) - S(-400 / 30))
+    assert np.max(np.abs(v - vex)) < 1e-11   # central-difference truncation ~ h^2 rho'''/6
+
+
+def test_trap_forces_are_minus_trap_energy_gradient():
+    rng = np.random.default_rng(16)
+    n = 14
+    R0 = oracle.polygon(5.0, 6.0, 3.0, n) + rng.normal(scale=0.1, size=(n, 2))
+    k, eps, leq = 0.05, 0.01, 1.3
+    t = 300.0
+    b = oracle.Body(R=R0.copy(), k_spring=k, eps_angle=eps, l_eq=leq, trap=TRAP)
+    f = b.forces(t)
+    kt, e = b.trap_k(t), b.trap_pos(t)
+
+    def U(R):   # elastic energy plus k(t)/2 |R_ext - mean R|^2, written out here
+        c = R.mean(axis=0)
+        return _energy_numpy(R, k, eps, leq) + 0.5 * kt * float(np.sum((e - c) ** 2))
+    h = 1e-6
+    for a in range(n):
+        for c in range(2):
+            Rp = R0.copy(); Rp[a, c] += h
+            Rm = R0.copy(); Rm[a, c] -= h
+            assert abs(f[a, c] + (U(Rp) - U(Rm)) / (2 * h)) < 1e-8
+    # the internal forces cancel: the total is the trap force on the centre of mass
+    assert np.max(np.abs(f.sum(axis=0) - kt * (e - R0.mean(axis=0)))) < 1e-15
+    assert abs(b.trap_energy(t) - 0.5 * kt * float(np.sum((e - R0.mean(axis=0)) ** 2))) < 1e-15
