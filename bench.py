@@ -175,7 +175,7 @@ def cpu_baseline(w, name: str, budget_s: float = 15.0):
     s = w.sims[0]
     p = s.params
     bodies = [oracle.Body(R=b.R.copy(), k_spring=b.k_spring, eps_angle=b.eps_angle, l_eq=b.l_eq, pull=b.pull,
-                          t_on=b.t_on, t_off=b.t_off, width=b.width) for b in s.bodies]
+                          t_on=b.t_on, t_off=b.t_off, width=b.width, trap=b.trap) for b in s.bodies]
     sim = oracle.Sim(dict(nx=s.nx, ny=s.ny, tau=p["tau"], Kx=p["Kx"], eta_p=p["eta_p"], D_p=p["D_p"], xi=p["xi"],
                           alpha=p["alpha"], beta=p["beta"], kappa=p["kappa"], Gamma=p["Gamma"],
                           P_clamp=p["P_clamp"], ericksen=p["ericksen"]), bodies=bodies, P=s.P0.copy())

@@ -50,8 +50,17 @@ typedef struct {
     double cx, cy, radius;      /* regular polygon, node a at angle 2 pi a / n_nodes */
     int32_t n_nodes;            /* 3 .. 1024 */
     double k_spring, eps_angle, l_eq;
-    double pull_fx, pull_fy;
+    double pull_fx, pull_fy;    /* constant total pull, shared equally by the nodes, switched on and
+                                   off by logistics of scale pull_width (<= 0: always on) centred
+                                   at pull_t_on and pull_t_off (steps) */
     double pull_t_on, pull_t_off, pull_width;
+    /* harmonic trap on the centre of mass (App. A, eqUtrap), trap_k = 0: none.  Stiffness
+     * k(t) = trap_k [S((t - t1)/w) - S((t - t2)/w)] with S the logistic function; position
+     * R_ext(t) = (trap_x0, trap_y0) + (trap_dx, trap_dy) rho(t) with
+     * rho(t) = w / (t2 - t1) [sp((t - t1)/w) - sp((t - t2)/w)], sp(x) = ln(1 + e^x): the trap
+     * moves the distance (trap_dx, trap_dy) at constant speed between t1 and t2 with logistic
+     * starts and stops, and lets go at t2.  Each node gets k(t) (R_ext - R_com) / n_nodes. */
+    double trap_k, trap_x0, trap_y0, trap_dx, trap_dy, trap_t1, trap_t2, trap_w;
     const double *nodes;        /* optional host array of 2*n_nodes unwrapped positions
                                    (x0, y0, x1, y1, ...) replacing the polygon; may be NULL */
 } lb_body_desc;
@@ -136,7 +145,7 @@ int lb_read_fields(lb_handle *h, int32_t sim, uint32_t field_mask, double *host_
 
 /* Body observables at the current time, FP64 (synchronous):
  * out[0..1] restoring force: sum of div sigma^p over the lattice sites inside the node polygon;
- * out[2..3] the current external pull; out[4..5] centre of mass of the nodes;
+ * out[2..3] the current external force (pull plus trap); out[4..5] centre of mass of the nodes;
  * out[6..7] total force the nodes apply to the fluid (sum_a f_a). */
 int lb_body_force(lb_handle *h, int32_t sim, int32_t body, double out[8]);
 

@@ -258,6 +258,8 @@ int validate(const lb_sim_params *sims, int n_sims, const Opt &o) {
             const lb_body_desc &d = p.bodies[b];
             if (d.n_nodes < 3 || d.n_nodes > kMaxNodes) return fail(LB_EINVAL, "sim %d body %d: n_nodes out of range", s, b);
             if (!d.nodes && !(d.radius > 0.0)) return fail(LB_EINVAL, "sim %d body %d: radius must be positive", s, b);
+            if (d.trap_k != 0.0 && (!(d.trap_w > 0.0) || !(d.trap_t2 >= d.trap_t1) || !std::isfinite(d.trap_k)))
+                return fail(LB_EINVAL, "sim %d body %d: trap needs trap_w > 0 and trap_t2 >= trap_t1", s, b);
             double ext = body_extent(d);
             int ps = 2 * (int)std::ceil(ext) + 24;
             int lim = std::min(p.nx, p.ny);
@@ -850,6 +852,14 @@ static int create_impl(const lb_sim_params *sims, int n_sims, const lb_options *
             B.t_on = bd.pull_t_on;
             B.t_off = bd.pull_t_off;
             B.width = bd.pull_width;
+            B.trap_k = bd.trap_k;
+            B.trap_x0 = bd.trap_x0;
+            B.trap_y0 = bd.trap_y0;
+            B.trap_dx = bd.trap_dx;
+            B.trap_dy = bd.trap_dy;
+            B.trap_t1 = bd.trap_t1;
+            B.trap_t2 = bd.trap_t2;
+            B.trap_w = bd.trap_w;
             B.R[0] = A.ptr<double>(bp.oR0);
             B.R[1] = A.ptr<double>(bp.oR1);
             B.fnode = A.ptr<double>(bp.oF);
@@ -1031,15 +1041,24 @@ int lb_read_fields(lb_handle *h, int32_t sim, uint32_t mask, double *out, size_t
 }
 
 static void body_out(const lb_handle *h, const BodyDev &B, const double *r, double *out) {
+    const double t = (double)h->t;
     double pf = 1.0;
-    if (B.width > 0.0) {
-        double t = (double)h->t;
+    if (B.width > 0.0)
         pf = 1.0 / (1.0 + std::exp(-(t - B.t_on) / B.width)) - 1.0 / (1.0 + std::exp(-(t - B.t_off) / B.width));
+    double ex = pf * B.fx, ey = pf * B.fy;
+    if (B.trap_k != 0.0) {   // k(t) (R_ext(t) - R_com), with R_com = r[2..3]
+        auto S = [](double x) { return 1.0 / (1.0 + std::exp(-x)); };
+        auto sp = [](double x) { return x > 30.0 ? x + std::log1p(std::exp(-x)) : std::log1p(std::exp(x)); };
+        const double w = B.trap_w, T = B.trap_t2 - B.trap_t1;
+        const double k = B.trap_k * (S((t - B.trap_t1) / w) - S((t - B.trap_t2) / w));
+        const double rho = T > 0.0 ? (w / T) * (sp((t - B.trap_t1) / w) - sp((t - B.trap_t2) / w)) : 0.0;
+        ex += k * (B.trap_x0 + B.trap_dx * rho - r[2]);
+        ey += k * (B.trap_y0 + B.trap_dy * rho - r[3]);
     }
     out[0] = r[0];
     out[1] = r[1];
-    out[2] = pf * B.fx;
-    out[3] = pf * B.fy;
+    out[2] = ex;
+    out[3] = ey;
     out[4] = r[2];
     out[5] = r[3];
     out[6] = r[4];

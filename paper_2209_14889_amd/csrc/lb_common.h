@@ -50,6 +50,7 @@ struct SimDev {
 struct BodyDev {
     int sim, n, ps, nside;          // owning sim, nodes, patch side, gather blocks per side
     double k, eps, leq, fx, fy, t_on, t_off, width;
+    double trap_k, trap_x0, trap_y0, trap_dx, trap_dy, trap_t1, trap_t2, trap_w;   // harmonic trap
     double *R[2];                   // node positions by step parity, interleaved x, y
     double *fnode;                  // node forces at the current time (2n)
     int *origin;                    // patch origin by step parity: [parity][4] = unwrapped x, y

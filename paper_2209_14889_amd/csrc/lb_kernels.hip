@@ -91,20 +91,6 @@ __device__ __forceinline__ double2 spring_pull(const double2 *R, int i, int j, d
 }
 
 // -dU/dR_a for U = sum springs + sum bending (eqConst), plus the pull share
-__device__ __forceinline__ double2 node_force(const BodyDev &B, const double2 *R, int a, double pf) {
-    const int n = B.n;
-    int am = a == 0 ? n - 1 : a - 1, ap = a == n - 1 ? 0 : a + 1;
-    double2 s1 = spring_pull(R, a, ap, B.k, B.leq);
-    double2 s0 = spring_pull(R, a, am, B.k, B.leq);
-    double2 d1a, d2a, d1m, d2m, d1p, d2p;
-    angle_grads(R, n, a, d1a, d2a);
-    angle_grads(R, n, am, d1m, d2m);
-    angle_grads(R, n, ap, d1p, d2p);
-    double fx = s1.x + s0.x + B.eps * ((d1a.x + d2a.x) - d2m.x - d1p.x) + pf * B.fx / n;
-    double fy = s1.y + s0.y + B.eps * ((d1a.y + d2a.y) - d2m.y - d1p.y) + pf * B.fy / n;
-    return make_double2(fx, fy);
-}
-
 __device__ __forceinline__ double wave_min(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
     return v;
@@ -118,6 +104,53 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// centre of mass of the n nodes in LDS, the same in every block: per-thread sums in node order,
+// wave sums, then the four waves in a fixed order (256-thread blocks)
+__device__ __forceinline__ double2 block_com(const double2 *sR, int n, double (*sC)[2]) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    double cx = 0.0, cy = 0.0;
+    for (int a = tid; a < n; a += 256) {
+        cx += sR[a].x;
+        cy += sR[a].y;
+    }
+    cx = wave_sum(cx);
+    cy = wave_sum(cy);
+    if (lane == 0) {
+        sC[wv][0] = cx;
+        sC[wv][1] = cy;
+    }
+    __syncthreads();
+    return make_double2(((sC[0][0] + sC[1][0]) + (sC[2][0] + sC[3][0])) / n,
+                        ((sC[0][1] + sC[1][1]) + (sC[2][1] + sC[3][1])) / n);
+}
+
+// each node's share k(t) (R_ext(t) - R_com) / n of the harmonic trap (App. A, eqUtrap): stiffness
+// switched by logistics, trap moved by their integral (a smoothed constant-speed ramp)
+__device__ __forceinline__ double2 trap_share(const BodyDev &B, double t, double2 com) {
+    if (B.trap_k == 0.0) return make_double2(0.0, 0.0);
+    const double w = B.trap_w, T = B.trap_t2 - B.trap_t1;
+    const double u1 = (t - B.trap_t1) / w, u2 = (t - B.trap_t2) / w;
+    const double k = B.trap_k * (1.0 / (1.0 + exp(-u1)) - 1.0 / (1.0 + exp(-u2)));
+    auto sp = [](double x) { return x > 30.0 ? x + log1p(exp(-x)) : log1p(exp(x)); };
+    const double rho = T > 0.0 ? (w / T) * (sp(u1) - sp(u2)) : 0.0;
+    return make_double2(k * (B.trap_x0 + B.trap_dx * rho - com.x) / B.n, k * (B.trap_y0 + B.trap_dy * rho - com.y) / B.n);
+}
+
+__device__ __forceinline__ double2 node_force(const BodyDev &B, const double2 *R, int a, double pf, double2 trap) {
+    const int n = B.n;
+    int am = a == 0 ? n - 1 : a - 1, ap = a == n - 1 ? 0 : a + 1;
+    double2 s1 = spring_pull(R, a, ap, B.k, B.leq);
+    double2 s0 = spring_pull(R, a, am, B.k, B.leq);
+    double2 d1a, d2a, d1m, d2m, d1p, d2p;
+    angle_grads(R, n, a, d1a, d2a);
+    angle_grads(R, n, am, d1m, d2m);
+    angle_grads(R, n, ap, d1p, d2p);
+    double fx = s1.x + s0.x + B.eps * ((d1a.x + d2a.x) - d2m.x - d1p.x) + pf * B.fx / n + trap.x;
+    double fy = s1.y + s0.y + B.eps * ((d1a.y + d2a.y) - d2m.y - d1p.y) + pf * B.fy / n + trap.y;
+    return make_double2(fx, fy);
+}
+
+
 // Two-launch body update for many bodies (each node advanced once): k_ib_nodes, then k_ib_spread.
 // One block per body.  ADVANCE: move the nodes from R(t) to R(t+1) by Heun with the velocity patch
 // written during step t (App. A: overdamped, no slip); otherwise take R[cur] as it is.  Then the
@@ -128,6 +161,7 @@ __global__ __launch_bounds__(256) void k_ib_nodes(const SimDev *__restrict__ sim
                                                   int cur, const int *__restrict__ d_t, int *__restrict__ d_status) {
     __shared__ double2 sR[kMaxNodes];
     __shared__ double sRed[4][4];
+    __shared__ double sC[4][2];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const BodyDev &B = bodies[blockIdx.x];
     const SimDev &S = sims[B.sim];
@@ -156,12 +190,13 @@ __global__ __launch_bounds__(256) void k_ib_nodes(const SimDev *__restrict__ sim
     __syncthreads();
 
     const double pf = pull_factor(B, (double)d_t[0]);
+    const double2 trap = trap_share(B, (double)d_t[0], block_com(sR, n, sC));
     double2 *Fn = reinterpret_cast<double2 *>(B.fnode);
     double2 *Rd = reinterpret_cast<double2 *>(B.R[dst]);
     double mnx = 1e300, mny = 1e300, mxx = -1e300, mxy = -1e300;
     for (int a = tid; a < n; a += 256) {
         const double2 R = sR[a];
-        Fn[a] = node_force(B, sR, a, pf);
+        Fn[a] = node_force(B, sR, a, pf, trap);
         if (ADVANCE) Rd[a] = R;
         int ix, iy;
         float wx[4], wy[4];
@@ -302,6 +337,7 @@ __global__ __launch_bounds__(256) void k_ib_step(const SimDev *__restrict__ sims
     __shared__ float4 sW[kMaxCand][2];
     __shared__ double2 sF[kMaxCand];
     __shared__ int sCnt[4];
+    __shared__ double sC[4][2];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int2 bt = blk[blockIdx.x];
     BodyDev &B = bodies[bt.x];
@@ -356,11 +392,12 @@ __global__ __launch_bounds__(256) void k_ib_step(const SimDev *__restrict__ sims
     if ((int)floor(mxx) + 3 - nox >= B.ps || (int)floor(mxy) + 3 - noy >= B.ps) bad = true;
 
     const double pf = pull_factor(B, (double)d_t[0]);
+    const double2 trap = trap_share(B, (double)d_t[0], block_com(sR, n, sC));
     if (lead) {
         double2 *Fn = reinterpret_cast<double2 *>(B.fnode);
         double2 *Rd = reinterpret_cast<double2 *>(B.R[dst]);
         for (int a = tid; a < n; a += 256) {
-            Fn[a] = node_force(B, sR, a, pf);
+            Fn[a] = node_force(B, sR, a, pf, trap);
             if (ADVANCE) Rd[a] = sR[a];
         }
         if (tid == 0) {
@@ -399,7 +436,7 @@ __global__ __launch_bounds__(256) void k_ib_step(const SimDev *__restrict__ sims
                 sI[q] = make_int2(ix - X0, iy - Y0);
                 sW[q][0] = make_float4(wx[0], wx[1], wx[2], wx[3]);
                 sW[q][1] = make_float4(wy[0], wy[1], wy[2], wy[3]);
-                sF[q] = node_force(B, sR, a, pf);
+                sF[q] = node_force(B, sR, a, pf, trap);
             } else {
                 overflow = true;
             }

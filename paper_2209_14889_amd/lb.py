@@ -31,6 +31,9 @@ class BodyDesc(ctypes.Structure):
         ("k_spring", ctypes.c_double), ("eps_angle", ctypes.c_double), ("l_eq", ctypes.c_double),
         ("pull_fx", ctypes.c_double), ("pull_fy", ctypes.c_double),
         ("pull_t_on", ctypes.c_double), ("pull_t_off", ctypes.c_double), ("pull_width", ctypes.c_double),
+        ("trap_k", ctypes.c_double), ("trap_x0", ctypes.c_double), ("trap_y0", ctypes.c_double),
+        ("trap_dx", ctypes.c_double), ("trap_dy", ctypes.c_double), ("trap_t1", ctypes.c_double),
+        ("trap_t2", ctypes.c_double), ("trap_w", ctypes.c_double),
         ("nodes", _dp),
     ]
 
@@ -147,6 +150,10 @@ class _Marshal:
             d.k_spring, d.eps_angle, d.l_eq = b.k_spring, b.eps_angle, b.l_eq
             d.pull_fx, d.pull_fy = b.pull
             d.pull_t_on, d.pull_t_off, d.pull_width = b.t_on, b.t_off, b.width
+            if getattr(b, "trap", None):
+                tr = b.trap
+                d.trap_k, d.trap_x0, d.trap_y0 = tr["k"], tr["x0"], tr["y0"]
+                d.trap_dx, d.trap_dy, d.trap_t1, d.trap_t2, d.trap_w = tr["dx"], tr["dy"], tr["t1"], tr["t2"], tr["w"]
             d.nodes = self._arr(b.R.reshape(-1))
             d.cx, d.cy = float(b.R[:, 0].mean()), float(b.R[:, 1].mean())
             d.radius = float(np.max(np.hypot(b.R[:, 0] - d.cx, b.R[:, 1] - d.cy)))

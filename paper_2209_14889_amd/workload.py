@@ -33,6 +33,7 @@ class BodySpec:
     t_on: float = 0.0                 # logistic switch-on centre (steps); width 0 = constant pull
     t_off: float = 0.0                # logistic switch-off centre (steps)
     width: float = 0.0                # logistic scale (steps)
+    trap: dict | None = None          # harmonic trap: k, x0, y0, dx, dy, t1, t2, w (include/lb.h)
 
 
 @dataclass
@@ -211,6 +212,38 @@ def small_case(seed: int, nx: int, ny: int, n_bodies: int = 1, radius: float = 5
         bodies.append(make_body(cx, cy, radius, nn, (pull * math.cos(ang), pull * math.sin(ang))))
     sim = SimSpec(nx, ny, base_params(relax, D_p, tau=tau, **over), director_field(th, math.sqrt(0.9)), bodies)
     return Workload(f"small{nx}x{ny}", [sim], 0, "fp32", dict(seed=seed))
+
+
+def trap_body(cx: float, cy: float, radius: float, d_pull: float, T_pull: float, k_trap: float,
+              t_rest: float = 30.0, width: float = 30.0, k_spring: float = 0.05) -> BodySpec:
+    """A body pulled along +x by the harmonic trap protocol (App. A, App. C): a t_rest rest, the
+    stiffness switched on by a logistic of scale `width` centred three scales later, the trap moved
+    d_pull at constant speed over T_pull with logistic starts and stops, then let go."""
+    b = make_body(cx, cy, radius, int(round(2 * math.pi * radius)), (0.0, 0.0), k_spring=k_spring)
+    c = b.R.mean(axis=0)
+    t1 = t_rest + 3.0 * width
+    b.trap = dict(k=k_trap, x0=float(c[0]), y0=float(c[1]), dx=float(d_pull), dy=0.0, t1=t1, t2=t1 + T_pull,
+                  w=width)
+    return b
+
+
+def trap_case(seed: int, nx: int, ny: int, radius: float = 6.0, d_pull: float = 4.0, T_pull: float = 800.0,
+              k_trap: float = 0.01, relax: float = 200.0, D_p: float = 0.01, walls: int = 1, P_eq: float = 0.0,
+              theta0: float = 0.0, **over) -> Workload:
+    """The paper's driven-droplet experiment at small size: one body pulled by the trap through the
+    polymer solution between walls, a uniform director at theta0 to the pull with magnitude P_eq
+    (alpha = -P_eq^2, beta = 1)."""
+    params = base_params(relax, D_p, walls=walls, alpha=-(P_eq * P_eq), beta=1.0, **over)
+    P0 = director_field(np.full((ny, nx), theta0), P_eq)
+    body = trap_body(nx / 2 - d_pull / 2, ny / 2, radius, d_pull, T_pull, k_trap)
+    return Workload(f"trap{nx}x{ny}", [SimSpec(nx, ny, params, P0, [body], meta=dict(seed=seed))], 0, "fp32",
+                    dict(d_pull=d_pull, T_pull=T_pull))
+
+
+def return_of(com_x0: float, com_x_end: float, d_pull: float) -> float:
+    """Return = 1 - d_rec / d_pull (Sec. III), d_rec the distance of the final centre of mass from
+    the initial one."""
+    return 1.0 - abs(com_x_end - com_x0) / d_pull
 
 
 WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4}

@@ -21,7 +21,8 @@ def oracle_params(sim: "wl.SimSpec", **over) -> dict:
 
 def oracle_sim(sim: "wl.SimSpec", **over) -> oracle.Sim:
     bodies = [oracle.Body(R=b.R.copy(), k_spring=b.k_spring, eps_angle=b.eps_angle, l_eq=b.l_eq,
-                          pull=b.pull, t_on=b.t_on, t_off=b.t_off, width=b.width) for b in sim.bodies]
+                          pull=b.pull, t_on=b.t_on, t_off=b.t_off, width=b.width, trap=b.trap)
+              for b in sim.bodies]
     sig = sim.sigma0 if sim.sigma0 is not None else None
     return oracle.Sim(oracle_params(sim, **over), bodies=bodies, P=sim.P0.copy(), sigma=sig)
 

@@ -70,3 +70,29 @@ def test_walls_fp16_storage():
         e = linf_rel(gf[k], of[k])
         say(f"  {k} {e:.2e}")
         assert e <= 1e-3, k
+
+
+@pytest.mark.parametrize("walls", [1, 0], ids=["walls", "periodic"])
+def test_trap_protocol_parity(walls):
+    """The harmonic trap (App. A) through its switch-on, the pull and the release, against the
+    oracle: fields, nodes and the external force the body feels."""
+    w = wl.trap_case(49, 64, 48, d_pull=4.0, T_pull=600.0, k_trap=0.01, walls=walls, P_eq=0.9,
+                     theta0=0.4)
+    say(f"case trap walls={walls} 64x48 seed=49 steps 150/700/900")
+    g = lb.Sim(w, lb.make_options(seg_rows=12))
+    r = oracle_sim(w.sims[0])
+    for n in (150, 550, 200):
+        g.step(n)
+        r.run(n)
+        gf, of = g.fields(), r.observe()
+        errs = {k: linf_rel(gf[k], of[k]) for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py")}
+        say(f" t={r.t}", {k: f"{v:.1e}" for k, v in errs.items()})
+        for k, e in errs.items():
+            assert e <= 1e-4, (k, e)
+        body = r.bodies[0]
+        assert np.max(np.abs(g.nodes()[0] - body.R)) <= 1e-5
+        com = body.R.mean(axis=0)
+        fext = body.trap_k(r.t) * (body.trap_pos(r.t) - com)
+        bf = g.body_force()
+        say("  external force gpu", bf["pull"], "oracle", fext)
+        assert np.max(np.abs(bf["pull"] - fext)) <= 1e-4 * max(np.max(np.abs(fext)), 1e-12) + 1e-12
