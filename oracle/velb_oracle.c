@@ -16,7 +16,7 @@
  *   4. molecular field h(P), Ericksen stress sigma^E and f^E = div sigma^E (Sec. II C 1);
  *   5. moments rho = sum h, rho v = sum c h + F/2 (eqrhoDef, eqvDef with Guo's half-force);
  *   6. BGK collision (eqBGK) with the standard second-order D2Q9 equilibrium and Guo forcing;
- *   7. streaming (eqLB), periodic, or halfway bounce-back at y walls (App. C boundary text);
+ *   7. streaming (eqLB), periodic, or halfway bounce-back at walls (App. C boundary text);
  *   8. velocity gradient, its symmetric part Psi and vorticity Omega (Sec. II B);
  *   9. stiffness C~(P) from the von Mises closure (eqPk) and the App. B closed form;
  *  10. Heun (predictor-corrector) step of the tensorial stress equation eqStiffCons with the
@@ -66,21 +66,25 @@ static inline int wrap(int i, int n) {
 
 enum { GHOST_EVEN = 0, GHOST_ODD = 1 };
 
-/* value of plane f at (x, y).  x is always periodic.  y is periodic, or with walls the ghost
- * row mirrors the first interior row: EVEN for zero-normal-derivative fields (stress,
- * polarization, App. C), ODD for the velocity (no-slip wall half way between the rows). */
+/* value of plane f at (x, y).  Periodic directions wrap.  Beyond a wall (y with walls >= 1, x
+ * with walls == 2) the ghost mirrors the first interior row or column: EVEN for
+ * zero-normal-derivative fields (stress, polarization, App. C), ODD for the velocity (no-slip wall
+ * half way between the sites). */
 static inline double at(const orc_params *p, const double *f, int x, int y, int ghost) {
-    x = wrap(x, p->nx);
-    if (!p->walls) return f[(size_t)wrap(y, p->ny) * p->nx + x];
-    if (y < 0) {
-        double v = f[(size_t)(-1 - y) * p->nx + x];
-        return ghost == GHOST_ODD ? -v : v;
+    double sign = 1.0;
+    if (p->walls == 2 && (x < 0 || x >= p->nx)) {
+        x = x < 0 ? -1 - x : 2 * p->nx - 1 - x;
+        if (ghost == GHOST_ODD) sign = -sign;
+    } else {
+        x = wrap(x, p->nx);
     }
-    if (y >= p->ny) {
-        double v = f[(size_t)(2 * p->ny - 1 - y) * p->nx + x];
-        return ghost == GHOST_ODD ? -v : v;
+    if (p->walls && (y < 0 || y >= p->ny)) {
+        y = y < 0 ? -1 - y : 2 * p->ny - 1 - y;
+        if (ghost == GHOST_ODD) sign = -sign;
+    } else {
+        y = wrap(y, p->ny);
     }
-    return f[(size_t)y * p->nx + x];
+    return sign * f[(size_t)y * p->nx + x];
 }
 
 static inline double ddx(const orc_params *p, const double *f, int x, int y, int g) {
@@ -297,6 +301,7 @@ void orc_spread(const orc_params *p, int n, const double *R, const double *f, do
             double wy = orc_phi(R[2 * a + 1] - y);
             for (int i = 0; i < 4; ++i) {
                 int x = x0 + i;
+                if (p->walls == 2 && (x < 0 || x >= p->nx)) continue;
                 double w = orc_phi(R[2 * a] - x) * wy;
                 size_t s = (size_t)wrap(y, p->ny) * p->nx + wrap(x, p->nx);
                 fx[s] += f[2 * a] * w;
@@ -316,6 +321,7 @@ void orc_interp(const orc_params *p, int n, const double *R, const double *ux, c
             double wy = orc_phi(R[2 * a + 1] - y);
             for (int i = 0; i < 4; ++i) {
                 int x = x0 + i;
+                if (p->walls == 2 && (x < 0 || x >= p->nx)) continue;
                 double w = orc_phi(R[2 * a] - x) * wy;
                 size_t s = (size_t)wrap(y, p->ny) * p->nx + wrap(x, p->nx);
                 vx += ux[s] * w;
@@ -460,7 +466,7 @@ static void collide_stream(const orc_params *p, double *h, work_t *w) {
                 /* pull form of h_n(r + c_n, t+1) = h*_n(r, t): the value arriving at (x, y) */
                 int xs = x - CX[n], ys = y - CY[n];
                 double v;
-                if (p->walls && (ys < 0 || ys >= ny))
+                if ((p->walls && (ys < 0 || ys >= ny)) || (p->walls == 2 && (xs < 0 || xs >= nx)))
                     v = w->hpost[(size_t)OPP[n] * N + s];     /* bounced back at the wall */
                 else
                     v = w->hpost[(size_t)n * N + (size_t)wrap(ys, ny) * nx + wrap(xs, nx)];

@@ -23,7 +23,8 @@ extern "C" {
 
 typedef struct {
     int nx, ny;
-    int walls;          /* 0: periodic in x and y; 1: halfway bounce-back walls at y=-1/2 and y=ny-1/2 */
+    int walls;          /* 0: periodic in x and y; 1: halfway bounce-back walls at y=-1/2 and y=ny-1/2;
+                           2: a closed box, walls also at x=-1/2 and x=nx-1/2 */
     double tau;         /* BGK relaxation time */
     double Kx[4];       /* K1111, K1122, K2222, K1212 of the aligned stiffness tensor */
     double eta_p;       /* polymer viscosity; +inf switches the relaxation term off */

@@ -94,3 +94,63 @@ def test_rest_state_is_stationary():
     h0 = s.h.copy()
     s.run(10)
     assert np.max(np.abs(s.h - h0)) < 1e-15
+
+
+# --- the closed box (walls on all four sides) -----------------------------------------------
+
+# D2Q9 directions under the reflection x <-> y: c_n = (cx, cy) -> (cy, cx)
+TRANSPOSE_DIR = [0, 2, 1, 4, 3, 5, 8, 7, 6]
+
+
+def _box_state(seed, n):
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + 0.01 * rng.standard_normal((n, n))
+    ux, uy = 0.01 * rng.standard_normal((2, n, n))
+    h = oracle.equilibrium(rho, ux, uy)
+    sigma = 1e-4 * rng.standard_normal((3, n, n))
+    th = rng.uniform(0, math.pi, (n, n))
+    P = 0.9 * np.stack([np.cos(th), np.sin(th)])
+    R = oracle.polygon(n / 2 + 0.3, n / 2 - 0.7, 4.0, 25) + 0.1 * rng.standard_normal((25, 2))
+    return h, sigma, P, R
+
+
+def _transpose_state(h, sigma, P, R):
+    hT = np.empty_like(h)
+    for q in range(9):
+        hT[TRANSPOSE_DIR[q]] = h[q].T
+    sT = np.stack([sigma[1].T, sigma[0].T, sigma[2].T])
+    PT = np.stack([P[1].T, P[0].T])
+    return hT, sT, PT, R[:, ::-1].copy()
+
+
+@pytest.mark.parametrize("walls", [2, 0])
+def test_reflection_across_the_diagonal(walls):
+    """x <-> y reflection covariance of the whole coupled step (the aligned stiffness is even in
+    y, so the law is covariant): the reflected initial state gives the reflected fields.  With
+    walls = 2 this pins the x-walls against the y-walls."""
+    n = 24
+    h, sigma, P, R = _box_state(5, n)
+    hT, sT, PT, RT = _transpose_state(h, sigma, P, R)
+    par = dict(nx=n, ny=n, walls=walls, D_p=0.02, eta_p=2.0, gx=3e-6, gy=-1e-6)
+    parT = dict(par, gx=-1e-6, gy=3e-6)
+    bA = oracle.Body(R=R, k_spring=0.05, eps_angle=0.01, l_eq=1.0, pull=(2e-4, 1e-4))
+    bB = oracle.Body(R=RT, k_spring=0.05, eps_angle=0.01, l_eq=1.0, pull=(1e-4, 2e-4))
+    a = oracle.Sim(par, bodies=[bA], h=h, sigma=sigma, P=P).run(30)
+    b = oracle.Sim(parT, bodies=[bB], h=hT, sigma=sT, P=PT).run(30)
+    oa, ob = a.observe(), b.observe()
+    assert np.max(np.abs(ob["vx"] - oa["vy"].T)) < 1e-15 + 1e-12 * np.abs(oa["vy"]).max()
+    assert np.max(np.abs(ob["vy"] - oa["vx"].T)) < 1e-15 + 1e-12 * np.abs(oa["vx"]).max()
+    assert np.max(np.abs(b.sigma[0] - a.sigma[1].T)) < 1e-12 * np.abs(a.sigma).max()
+    assert np.max(np.abs(b.sigma[2] - a.sigma[2].T)) < 1e-12 * np.abs(a.sigma).max()
+    assert np.max(np.abs(b.P[0] - a.P[1].T)) < 1e-12
+    assert np.max(np.abs(bB.R - bA.R[:, ::-1])) < 1e-12
+
+
+def test_box_conserves_mass():
+    n = 20
+    h, sigma, P, R = _box_state(6, n)
+    s = oracle.Sim(dict(nx=n, ny=n, walls=2, gx=1e-5), bodies=[oracle.Body(R=R, pull=(1e-4, 0.0))],
+                   h=h, sigma=sigma, P=P)
+    m0 = s.h.sum()
+    s.run(50)
+    assert abs(s.h.sum() - m0) < 1e-12 * m0
