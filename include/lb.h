@@ -75,12 +75,14 @@ typedef struct {
     double xi, alpha, beta, kappa, Gamma;  /* Beris-Edwards and free energy (eqBE, eqFfunctional) */
     double P_clamp;             /* magnitude cap when inverting P(k) (eqPk), in (0, 1) */
     int32_t ericksen;           /* 1: the Ericksen force enters F (the paper's model) */
-    int32_t walls;              /* 0: periodic in y; 1: walls half a site below row 0 and above row
-                                   ny-1 (App. C): halfway bounce-back of the populations, mirror
-                                   ghosts for sigma, P and the Ericksen stress, odd (no-slip)
-                                   ghosts for the velocity gradient.  x is always periodic.  Every
-                                   node's 4x4 kernel footprint must stay inside the rows with one
-                                   row to spare (LB_EINVAL in lb_create, LB_ERANGE later) */
+    int32_t walls;              /* 0: periodic; 1: walls half a site below row 0 and above row ny-1,
+                                   x periodic (a channel); 2: also half a site left of column 0 and
+                                   right of column nx-1 (a closed box, the paper's geometry).  At a
+                                   wall (App. C): halfway bounce-back of the populations, mirror
+                                   ghosts for sigma, P and the Ericksen stress, odd (no-slip) ghosts
+                                   for the velocity gradient.  Every node's 4x4 kernel footprint
+                                   must stay inside the walls with one site to spare (LB_EINVAL in
+                                   lb_create, LB_ERANGE later) */
     double gx, gy;              /* uniform body force density added to F at every site */
     int32_t n_bodies;           /* 0 .. 64 */
     const lb_body_desc *bodies;

@@ -250,7 +250,7 @@ int validate(const lb_sim_params *sims, int n_sims, const Opt &o) {
         if (!(p.D_p >= 0.0) || !(8.0 * p.D_p < 2.0)) return fail(LB_EINVAL, "sim %d: need 0 <= D_p and 8 D_p < 2", s);
         if (!(p.eta_p > 0.0)) return fail(LB_EINVAL, "sim %d: eta_p must be positive", s);
         if (!(p.P_clamp > 0.0 && p.P_clamp < 1.0)) return fail(LB_EINVAL, "sim %d: P_clamp must be in (0, 1)", s);
-        if (p.walls != 0 && p.walls != 1) return fail(LB_EINVAL, "sim %d: walls must be 0 or 1", s);
+        if (p.walls < 0 || p.walls > 2) return fail(LB_EINVAL, "sim %d: walls must be 0, 1 or 2", s);
         if (!std::isfinite(p.gx) || !std::isfinite(p.gy)) return fail(LB_EINVAL, "sim %d: gx, gy must be finite", s);
         if (p.n_bodies < 0 || p.n_bodies > kMaxBodies) return fail(LB_EINVAL, "sim %d: n_bodies out of range", s);
         if (p.n_bodies > 0 && !p.bodies) return fail(LB_EINVAL, "sim %d: bodies is NULL", s);
@@ -277,7 +277,16 @@ int validate(const lb_sim_params *sims, int n_sims, const Opt &o) {
                         hi = std::max(hi, d.nodes[2 * a + 1]);
                     }
                 }
-                if (std::floor(lo) - 2 < 0 || std::floor(hi) + 3 > p.ny - 1)
+                double lox = d.cx - ext, hix = d.cx + ext;
+                if (d.nodes) {
+                    lox = hix = d.nodes[0];
+                    for (int a = 0; a < d.n_nodes; ++a) {
+                        lox = std::min(lox, d.nodes[2 * a]);
+                        hix = std::max(hix, d.nodes[2 * a]);
+                    }
+                }
+                if (std::floor(lo) - 2 < 0 || std::floor(hi) + 3 > p.ny - 1 ||
+                    (p.walls == 2 && (std::floor(lox) - 2 < 0 || std::floor(hix) + 3 > p.nx - 1)))
                     return fail(LB_EINVAL, "sim %d body %d: a node's kernel footprint reaches a wall", s, b);
             }
         }

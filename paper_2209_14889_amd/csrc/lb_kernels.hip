@@ -202,7 +202,8 @@ __global__ __launch_bounds__(256) void k_ib_nodes(const SimDev *__restrict__ sim
         float wx[4], wy[4];
         phi4(R.x, ix, wx);
         phi4(R.y, iy, wy);
-        if (S.walls && (iy < 1 || iy + 4 >= S.ny)) wall = true;   // one row of margin for the predictor position
+        if ((S.walls && (iy < 1 || iy + 4 >= S.ny)) || (S.walls == 2 && (ix < 1 || ix + 4 >= S.nx)))
+            wall = true;   // one site of margin for the predicted position
         B.nix[2 * a] = ix;
         B.nix[2 * a + 1] = iy;
         float4 *w = reinterpret_cast<float4 *>(B.nw) + 2 * a;
@@ -421,7 +422,8 @@ __global__ __launch_bounds__(256) void k_ib_step(const SimDev *__restrict__ sims
             const double2 R = sR[a];
             phi4(R.x, ix, wx);
             phi4(R.y, iy, wy);
-            if (S.walls && (iy < 1 || iy + 4 >= S.ny)) wall = true;   // one row of margin for the predictor position
+            if ((S.walls && (iy < 1 || iy + 4 >= S.ny)) || (S.walls == 2 && (ix < 1 || ix + 4 >= S.nx)))
+            wall = true;   // one site of margin for the predicted position
             flag = ix > X0 - 4 && ix < X0 + kPatchTile && iy > Y0 - 4 && iy < Y0 + kPatchTile;
         }
         const unsigned long long m = __ballot(flag);
@@ -557,6 +559,8 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
         // walls: the rows next to them, whose neighbour beyond is a ghost
         const bool walls = WALLS && S.walls != 0;   // the periodic variant has no wall code
         const unsigned ytop = ny - 1u;
+        // closed box: this lane's column is next to the west / east wall
+        const bool xw = WALLS && S.walls == 2 && x == 0u, xe = WALLS && S.walls == 2 && x == nx - 1u;
 
         // Loads for the next iteration, issued one iteration ahead.  Every lane loads (all
         // indices are wrapped into the lattice); lanes outside a stage's columns never use them.
@@ -624,14 +628,14 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                     const bool blo = walls && rm1 == 0u, bhi = walls && rm1 == ytop;
                     const unsigned own = yc + x;
                     pout.H[0] = Pop<HT>::ld_raw(hin, own);
-                    pout.H[1] = Pop<HT>::ld_raw(hin, N + yc + xm);
+                    pout.H[1] = Pop<HT>::ld_raw(hin, xw ? 3u * N + own : N + yc + xm);
                     pout.H[2] = Pop<HT>::ld_raw(hin, blo ? 4u * N + own : 2u * N + ym + x);
-                    pout.H[3] = Pop<HT>::ld_raw(hin, 3u * N + yc + xp);
+                    pout.H[3] = Pop<HT>::ld_raw(hin, xe ? N + own : 3u * N + yc + xp);
                     pout.H[4] = Pop<HT>::ld_raw(hin, bhi ? 2u * N + own : 4u * N + yp + x);
-                    pout.H[5] = Pop<HT>::ld_raw(hin, blo ? 7u * N + own : 5u * N + ym + xm);
-                    pout.H[6] = Pop<HT>::ld_raw(hin, blo ? 8u * N + own : 6u * N + ym + xp);
-                    pout.H[7] = Pop<HT>::ld_raw(hin, bhi ? 5u * N + own : 7u * N + yp + xp);
-                    pout.H[8] = Pop<HT>::ld_raw(hin, bhi ? 6u * N + own : 8u * N + yp + xm);
+                    pout.H[5] = Pop<HT>::ld_raw(hin, blo || xw ? 7u * N + own : 5u * N + ym + xm);
+                    pout.H[6] = Pop<HT>::ld_raw(hin, blo || xe ? 8u * N + own : 6u * N + ym + xp);
+                    pout.H[7] = Pop<HT>::ld_raw(hin, bhi || xe ? 5u * N + own : 7u * N + yp + xp);
+                    pout.H[8] = Pop<HT>::ld_raw(hin, bhi || xw ? 6u * N + own : 8u * N + yp + xm);
                 }
             }
             __syncthreads();
@@ -644,8 +648,8 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             if (j >= 2 && colB) {
                 const int an = walls && rm1 == ytop ? a1 : a0, as = walls && rm1 == 0u ? a1 : a2;
                 double Pc[2] = {rP[a1][0][tid], rP[a1][1][tid]};
-                double Pe[2] = {rP[a1][0][tid + 1], rP[a1][1][tid + 1]};
-                double Pw[2] = {rP[a1][0][tid - 1], rP[a1][1][tid - 1]};
+                double Pe[2] = {rP[a1][0][xe ? tid : tid + 1], rP[a1][1][xe ? tid : tid + 1]};
+                double Pw[2] = {rP[a1][0][xw ? tid : tid - 1], rP[a1][1][xw ? tid : tid - 1]};
                 double Pn[2] = {rP[an][0][tid], rP[an][1][tid]};
                 double Ps[2] = {rP[as][0][tid], rP[as][1][tid]};
                 float E[4];
@@ -661,13 +665,14 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             if (j >= 4 && colC) {
                 const bool clo = walls && rm2 == 0u, chi = walls && rm2 == ytop;
                 const int bn = chi ? b2 : b1, bs = clo ? b2 : b3;
-                float Fx = 0.5f * (rS[b2][0][tid + 1] - rS[b2][0][tid - 1]) + 0.5f * (rS[bn][2][tid] - rS[bs][2][tid]);
-                float Fy = 0.5f * (rS[b2][2][tid + 1] - rS[b2][2][tid - 1]) + 0.5f * (rS[bn][1][tid] - rS[bs][1][tid]);
+                const int te = xe ? tid : tid + 1, tw = xw ? tid : tid - 1;   // mirror ghosts at x walls
+                float Fx = 0.5f * (rS[b2][0][te] - rS[b2][0][tw]) + 0.5f * (rS[bn][2][tid] - rS[bs][2][tid]);
+                float Fy = 0.5f * (rS[b2][2][te] - rS[b2][2][tw]) + 0.5f * (rS[bn][1][tid] - rS[bs][1][tid]);
                 if (S.ericksen) {
                     const float exn = chi ? exy2 : exy1, exs = clo ? exy2 : exy3;
                     const float eyn = chi ? eyy2 : eyy1, eys = clo ? eyy2 : eyy3;
-                    Fx += 0.5f * (rE[o0][0][tid + 1] - rE[o0][0][tid - 1]) + 0.5f * (exn - exs);
-                    Fy += 0.5f * (rE[o0][1][tid + 1] - rE[o0][1][tid - 1]) + 0.5f * (eyn - eys);
+                    Fx += 0.5f * (rE[o0][0][te] - rE[o0][0][tw]) + 0.5f * (exn - exs);
+                    Fy += 0.5f * (rE[o0][1][te] - rE[o0][1][tw]) + 0.5f * (eyn - eys);
                 }
                 Fx += S.gx;
                 Fy += S.gy;
@@ -705,10 +710,12 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                     const bool dlo = walls && rm3 == 0u, dhi = walls && rm3 == ytop;
                     const float vxn = dhi ? -cout.vx : rV[o0][0][tid], vyn = dhi ? -cout.vy : rV[o0][1][tid];
                     const float vxs = dlo ? -cout.vx : cin.vx, vys = dlo ? -cout.vy : cin.vy;
-                    cout.g = grad_v(rV[o1][0][tid + 1], rV[o1][0][tid - 1], vxn, vxs,
-                                    rV[o1][1][tid + 1], rV[o1][1][tid - 1], vyn, vys);
-                    double Pe[2] = {rP[a3][0][tid + 1], rP[a3][1][tid + 1]};
-                    double Pw[2] = {rP[a3][0][tid - 1], rP[a3][1][tid - 1]};
+                    const int te = xe ? tid : tid + 1, tw = xw ? tid : tid - 1;
+                    const float sxe = xe ? -1.0f : 1.0f, sxw = xw ? -1.0f : 1.0f;   // no-slip ghosts
+                    cout.g = grad_v(sxe * rV[o1][0][te], sxw * rV[o1][0][tw], vxn, vxs,
+                                    sxe * rV[o1][1][te], sxw * rV[o1][1][tw], vyn, vys);
+                    double Pe[2] = {rP[a3][0][te], rP[a3][1][te]};
+                    double Pw[2] = {rP[a3][0][tw], rP[a3][1][tw]};
                     const int an = dhi ? a3 : a2;
                     double Pn[2] = {rP[an][0][tid], rP[an][1][tid]};
                     double Ps[2] = {dlo ? Pc[0] : cin.p0, dlo ? Pc[1] : cin.p1};
@@ -717,8 +724,8 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                     const int bn = dhi ? b3 : b2;
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
-                        Xe[q] = rS[b3][q][tid + 1];
-                        Xw[q] = rS[b3][q][tid - 1];
+                        Xe[q] = rS[b3][q][te];
+                        Xw[q] = rS[b3][q][tw];
                         Xn[q] = rS[bn][q][tid];
                     }
                     const float Xs[3] = {dlo ? X[0] : cin.s0, dlo ? X[1] : cin.s1, dlo ? X[2] : cin.s2};
@@ -751,18 +758,19 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                 if (j >= 8) {
                     const bool elo = walls && rm4 == 0u, ehi = walls && rm4 == ytop;
                     const int on = ehi ? o0 : o1;
+                    const int te = xe ? tid : tid + 1, tw = xw ? tid : tid - 1;
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
-                        Xe[q] = rQs[o0][q][tid + 1];
-                        Xw[q] = rQs[o0][q][tid - 1];
+                        Xe[q] = rQs[o0][q][te];
+                        Xw[q] = rQs[o0][q][tw];
                         Xn[q] = rQs[on][q][tid];
                     }
                     const float Xs[3] = {elo ? X[0] : cin.q0, elo ? X[1] : cin.q1, elo ? X[2] : cin.q2};
                     rhs_sigma(S, cin.k, cin.g, cin.vx, cin.vy, X, Xe, Xw, Xn, Xs, Rs);
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
-                        Ye[q] = rQp[o0][q][tid + 1];
-                        Yw[q] = rQp[o0][q][tid - 1];
+                        Ye[q] = rQp[o0][q][te];
+                        Yw[q] = rQp[o0][q][tw];
                         Yn[q] = rQp[on][q][tid];
                     }
                     const double Ys[2] = {elo ? Y[0] : cin.qp0, elo ? Y[1] : cin.qp1};
@@ -804,14 +812,17 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
 // ghost (the site itself: zero normal derivative), flagged in lo / hi for odd (no-slip) fields
 struct Nb {
     size_t c, e, w, n, s;
-    bool lo, hi;
+    bool lo, hi, le, ri;   // the south, north, west, east neighbour is a wall ghost
 };
+// walls: 1 below row 0 and above row ny-1; 2 also left of column 0 and right of column nx-1
 __device__ __forceinline__ Nb nbrs(int x, int y, int nx, int ny, int walls = 0) {
     Nb q;
     size_t row = (size_t)y * nx;
     q.c = row + x;
-    q.e = row + wrapi(x + 1, nx);
-    q.w = row + wrapi(x - 1, nx);
+    q.le = walls == 2 && x == 0;
+    q.ri = walls == 2 && x == nx - 1;
+    q.e = q.ri ? q.c : row + wrapi(x + 1, nx);
+    q.w = q.le ? q.c : row + wrapi(x - 1, nx);
     q.lo = walls && y == 0;
     q.hi = walls && y == ny - 1;
     q.n = q.hi ? q.c : (size_t)wrapi(y + 1, ny) * nx + x;
@@ -868,12 +879,13 @@ __device__ __forceinline__ void pull_pops(const SimDev &S, const HT *hin, int x,
     const size_t N = (size_t)S.nx * S.ny;
 #pragma unroll
     for (int n = 0; n < 9; ++n) {
-        const int ys = y - kCY[n];
-        if (S.walls && (ys < 0 || ys >= S.ny)) {   // halfway bounce-back: the opposite direction
+        const int ys = y - kCY[n], xs = x - kCX[n];
+        if ((S.walls && (ys < 0 || ys >= S.ny)) || (S.walls == 2 && (xs < 0 || xs >= S.nx))) {
+            // halfway bounce-back: the opposite direction
             d[n] = Pop<HT>::load(hin, kOpp[n] * N + (size_t)y * S.nx + x, S.inv_scale);   // at this site
             continue;
         }
-        size_t i = (size_t)wrapi(ys, S.ny) * S.nx + wrapi(x - kCX[n], S.nx);
+        size_t i = (size_t)wrapi(ys, S.ny) * S.nx + wrapi(xs, S.nx);
         d[n] = Pop<HT>::load(hin, n * N + i, S.inv_scale);
     }
 }
@@ -903,8 +915,9 @@ __device__ __forceinline__ Grad grad_at(const SimDev &S, const Nb &q) {
     const size_t N = (size_t)S.nx * S.ny;
     const float *v = S.v;
     // no-slip ghosts beyond a wall: the negated velocity of the wall row
-    const float sn = q.hi ? -1.0f : 1.0f, ss = q.lo ? -1.0f : 1.0f;
-    return grad_v(v[q.e], v[q.w], sn * v[q.n], ss * v[q.s], v[N + q.e], v[N + q.w], sn * v[N + q.n], ss * v[N + q.s]);
+    const float sn = q.hi ? -1.0f : 1.0f, ss = q.lo ? -1.0f : 1.0f, se = q.ri ? -1.0f : 1.0f, sw = q.le ? -1.0f : 1.0f;
+    return grad_v(se * v[q.e], sw * v[q.w], sn * v[q.n], ss * v[q.s], se * v[N + q.e], sw * v[N + q.w], sn * v[N + q.n],
+                  ss * v[N + q.s]);
 }
 
 __device__ __forceinline__ void gather3(const float *f, size_t N, const Nb &q, float X[3], float Xe[3], float Xw[3],

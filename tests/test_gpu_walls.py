@@ -96,3 +96,25 @@ def test_trap_protocol_parity(walls):
         bf = g.body_force()
         say("  external force gpu", bf["pull"], "oracle", fext)
         assert np.max(np.abs(bf["pull"] - fext)) <= 1e-4 * max(np.max(np.abs(fext)), 1e-12) + 1e-12
+
+
+@pytest.mark.parametrize("kernel", [0, 1], ids=["fused", "multipass"])
+def test_box_trap_parity(kernel):
+    """The closed box (walls on all four sides) with the trap protocol and a polarized director along
+    the pull, against the oracle through the pull and the release.  (With the director oblique to
+    the walls the Ericksen coupling makes the box corners unstable in the oracle itself, so the
+    FP32 and FP64 runs part ways; that case is exercised in the channel instead.)"""
+    w = wl.trap_case(51, 60, 44, radius=6.0, d_pull=4.0, T_pull=400.0, k_trap=0.5, walls=2, P_eq=0.9,
+                     theta0=0.0)
+    say(f"case box trap kernel={kernel} 60x44 seed=51 steps 300/600/900")
+    g = lb.Sim(w, lb.make_options(kernel=kernel, seg_rows=10))
+    r = oracle_sim(w.sims[0])
+    for n in (300, 300, 300):
+        g.step(n)
+        r.run(n)
+        gf, of = g.fields(), r.observe()
+        errs = {k: linf_rel(gf[k], of[k]) for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py")}
+        say(f" t={r.t}", {k: f"{v:.1e}" for k, v in errs.items()})
+        for k, e in errs.items():
+            assert e <= 1e-4, (k, e)
+        assert np.max(np.abs(g.nodes()[0] - r.bodies[0].R)) <= 1e-5

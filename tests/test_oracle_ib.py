@@ -243,3 +243,30 @@ def test_trap_forces_are_minus_trap_energy_gradient():
     # the internal forces cancel: the total is the trap force on the centre of mass
     assert np.max(np.abs(f.sum(axis=0) - kt * (e - R0.mean(axis=0)))) < 1e-15
     assert abs(b.trap_energy(t) - 0.5 * kt * float(np.sum((e - R0.mean(axis=0)) ** 2))) < 1e-15
+
+
+def _trap_run(Kx, k_trap=0.5):
+    from paper_2209_14889_amd import workload as wl
+    from tests.helpers import oracle_sim
+    w = wl.trap_case(50, 64, 48, radius=6.0, d_pull=4.0, T_pull=800.0, k_trap=k_trap, walls=2, Kx=Kx)
+    sim = oracle_sim(w.sims[0])
+    body = sim.bodies[0]
+    x0 = body.R[:, 0].mean()
+    xs = []
+    for _ in range(24):
+        sim.run(100)
+        xs.append(body.R[:, 0].mean() - x0)
+    return np.array(xs), wl.return_of(0.0, xs[-1], 4.0)
+
+
+def test_viscoelastic_return_in_a_box():
+    """The paper's experiment (Sec. III) in miniature: a droplet dragged 4 sites by the trap through
+    the polymer solution in a closed box and let go recoils towards its start (Return > 0); in
+    the Newtonian fluid (no polymer stiffness) it does not (it coasts a little further)."""
+    from paper_2209_14889_amd import workload as wl
+    xs_ve, ret_ve = _trap_run(wl.KX_TABLE_IV)
+    xs_nw, ret_nw = _trap_run((0.0, 0.0, 0.0, 0.0))
+    assert xs_ve.max() > 3.0 and xs_nw.max() > 3.5           # the trap drags both
+    assert xs_ve[-1] < xs_ve.max() - 0.5                       # elastic recoil
+    assert xs_nw[-1] > xs_nw.max() - 0.05                      # no recoil without elasticity
+    assert ret_ve > ret_nw + 0.25
