@@ -62,6 +62,10 @@ def workload(name: str, steps: int):
     if name == "c4":
         w = wl.c4(steps=steps)
         return w, "256-simulation ensemble, sizes {64..512}^2, one body each", 0
+    if name == "paper":
+        w = wl.paper_case()
+        return w, ("the paper's experiment (Tables I-IV): 250x250 closed box, tau 1.25, 157-node droplet dragged 100 "
+                   "sites over 25000 steps by the trap, 187500 steps"), 0
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -243,6 +247,7 @@ def main():
 
     import torch
     from paper_2209_14889_amd import lb
+    from paper_2209_14889_amd import workload as wl_mod
 
     w, desc, precision = workload(args.workload, args.steps)
     sites = w.sites
@@ -264,6 +269,17 @@ def main():
     dt = time.perf_counter() - t0
     mlups = sites * args.steps / dt / 1e6
     log(f"bench: {args.steps} steps in {dt:.4f} s -> {mlups:.1f} MLUPS")
+    experiment = None
+    if args.workload == "paper":
+        # the droplet's Return (Sec. III) once the whole protocol has run
+        b0 = w.sims[0].bodies[0]
+        com = sim.body_forces()[0, 4:6]
+        total = args.warmup + args.steps
+        ret = wl_mod.return_of(b0.trap["x0"], com[0], b0.trap["dx"]) if total >= wl_mod.PAPER_STEPS else None
+        experiment = {"steps": total, "timed_s": round(dt, 3), "return": None if ret is None else round(ret, 4),
+                      "final_com": [round(float(c), 4) for c in com],
+                      "paper_cpu_wall": "about 20 h for 187500 steps on one CPU core (App. C)"}
+        log(f"bench: paper experiment {experiment}")
     sim.close()
 
     # roofline of the dominant kernel: HIP events around every field-kernel launch on the
@@ -323,6 +339,8 @@ def main():
         "cpu_baseline": cpu,
         "surrogate": sur,
     }
+    if experiment is not None:
+        line["experiment"] = experiment
     print(json.dumps(line), flush=True)
 
 

@@ -449,6 +449,8 @@ struct lb_handle {
     int fused_T = 256;
     int fused_seg = 0;
     bool any_walls = false;   // some simulation has walls: launch the fused variant that handles them
+    bool any_pol = false;     // some simulation has a polarization field; if none, P stays 0 and the
+                              // fused variant without the P and Ericksen work runs
     int n_items = 0;
     float tuned_ms = 0.f;
     // graph replay
@@ -522,7 +524,7 @@ int launch_step(lb_handle *h, bool timed) {
         HIPCHK(hipEventRecord(a, h->stream));
     }
     if (h->opt.kernel == 0) {
-        HIPCHK(launch_fused(h->fused_T, fp16, h->any_walls, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
+        HIPCHK(launch_fused(h->fused_T, fp16, h->any_walls, h->any_pol, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
                             h->n_items, h->cur, h->d_t));
     } else {
         HIPCHK(launch_multipass(fp16, (int)h->plan.site_blk.size(), h->stream, h->d_sims, h->d_bodies, h->d_site,
@@ -589,7 +591,7 @@ int choose_fused_config(lb_handle *h) {
     };
     if (!h->opt.autotune) {
         int T = model_T();
-        int seg = h->opt.seg ? h->opt.seg : model_seg(h->plan.sims, T, cus * fused_blocks_per_cu(T, fp16, h->any_walls));
+        int seg = h->opt.seg ? h->opt.seg : model_seg(h->plan.sims, T, cus * fused_blocks_per_cu(T, fp16, h->any_walls, h->any_pol));
         return upload_items(h, T, seg, h->opt.grid);
     }
     struct Cand {
@@ -599,7 +601,7 @@ int choose_fused_config(lb_handle *h) {
     std::vector<Cand> cand;
     for (int T : {128, 256}) {
         if (h->opt.threads && T != h->opt.threads) continue;
-        int slots = cus * fused_blocks_per_cu(T, fp16, h->any_walls);
+        int slots = cus * fused_blocks_per_cu(T, fp16, h->any_walls, h->any_pol);
         int m = model_seg(h->plan.sims, T, slots);
         for (int seg : {m, std::max(4, m / 2), m * 2, m + 4, std::max(4, m - 4), 64}) {
             for (int grid : {0, (slots / 8) * 8}) {
@@ -619,7 +621,7 @@ int choose_fused_config(lb_handle *h) {
         int rc = upload_items(h, cand.front().T, cand.front().seg, cand.front().grid);
         if (rc) return rc;
         for (int r = 0; r < 30; ++r)
-            HIPCHK(launch_fused(cand.front().T, fp16, h->any_walls, h->fused_grid, h->stream, h->d_sims, h->d_bodies,
+            HIPCHK(launch_fused(cand.front().T, fp16, h->any_walls, h->any_pol, h->fused_grid, h->stream, h->d_sims, h->d_bodies,
                                 h->d_items, h->n_items, h->cur, h->d_t));
     }
     std::vector<float> tbest(cand.size(), 1e30f);
@@ -628,11 +630,11 @@ int choose_fused_config(lb_handle *h) {
             const Cand c = cand[ci];
             int rc = upload_items(h, c.T, c.seg, c.grid);
             if (rc) return rc;
-            HIPCHK(launch_fused(c.T, fp16, h->any_walls, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
+            HIPCHK(launch_fused(c.T, fp16, h->any_walls, h->any_pol, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
                                 h->n_items, h->cur, h->d_t));
             HIPCHK(hipEventRecord(e0, h->stream));
             for (int r = 0; r < 8; ++r)
-                HIPCHK(launch_fused(c.T, fp16, h->any_walls, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
+                HIPCHK(launch_fused(c.T, fp16, h->any_walls, h->any_pol, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
                                     h->n_items, h->cur, h->d_t));
             HIPCHK(hipEventRecord(e1, h->stream));
             HIPCHK(hipEventSynchronize(e1));
@@ -814,9 +816,11 @@ static int create_impl(const lb_sim_params *sims, int n_sims, const lb_options *
         // P (FP64) and sigma
         {
             std::vector<double> pb(2 * N, 0.0);
+            HIPCHK(hipMemcpyAsync(d.P[1], pb.data(), 2 * N * 8, hipMemcpyHostToDevice, h->stream));
             if (p.init_P) std::copy(p.init_P, p.init_P + 2 * N, pb.begin());
             HIPCHK(hipMemcpyAsync(d.P[0], pb.data(), 2 * N * 8, hipMemcpyHostToDevice, h->stream));
             HIPCHK(hipStreamSynchronize(h->stream));
+            for (double v : pb) h->any_pol = h->any_pol || v != 0.0;
         }
         buf.assign(3 * N, 0.0f);
         if (p.init_sigma)
@@ -828,14 +832,25 @@ static int create_impl(const lb_sim_params *sims, int n_sims, const lb_options *
         static const int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
         static const int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
         static const double WQ[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+        static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
         buf.assign(9 * N, 0.0f);
         if (p.init_h) {
             for (int n = 0; n < 9; ++n)
                 for (int y = 0; y < p.ny; ++y)
                     for (int x = 0; x < p.nx; ++x) {
-                        int xs = (x + CX[n] + p.nx) % p.nx, ys = (y + CY[n] + p.ny) % p.ny;
+                        int xs = x + CX[n], ys = y + CY[n];
+                        // beyond a wall the first pull bounces back: this slot is then read as
+                        // the opposite direction at (x, y)
+                        const bool out = (p.walls && (ys < 0 || ys >= p.ny)) || (p.walls == 2 && (xs < 0 || xs >= p.nx));
+                        const int m = out ? OPP[n] : n;
+                        if (out) {
+                            xs = x;
+                            ys = y;
+                        }
+                        xs = (xs + p.nx) % p.nx;
+                        ys = (ys + p.ny) % p.ny;
                         buf[(size_t)n * N + (size_t)y * p.nx + x] =
-                            (float)(p.init_h[(size_t)n * N + (size_t)ys * p.nx + xs] - WQ[n]);
+                            (float)(p.init_h[(size_t)m * N + (size_t)ys * p.nx + xs] - WQ[n]);
                     }
         }
         HIPCHK(hipMemcpyAsync(h->d_stage, buf.data(), 9 * N * 4, hipMemcpyHostToDevice, h->stream));

@@ -485,18 +485,22 @@ __device__ __forceinline__ int xcd_remap(int v, int n) {
 
 __device__ __forceinline__ void inc_row(unsigned &r, unsigned ny) { r = (r + 1u == ny) ? 0u : r + 1u; }
 
-template <int T, typename HT, bool WALLS>
+// POL = false: every simulation of the launch has P = 0, which the dynamics keep exactly (the
+// polarization right-hand side is proportional to P), so the Ericksen stress vanishes and C~ is
+// its isotropic value: the scalar model of Sec. II B.  That variant skips all P work.
+template <int T, typename HT, bool WALLS, bool POL>
 __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, const BodyDev *__restrict__ bodies,
                                              const WorkItem *__restrict__ items, int n_items, int cur,
                                              int *__restrict__ d_t) {
     // row-exchange rings; values a thread needs only from its own column one row below live in
     // registers (the "carried" row of the previous iteration)
-    __shared__ double rP[4][2][T];   // polarization rows f-3 .. f
-    __shared__ float rS[3][3][T];    // stress rows f-3 .. f-1
-    __shared__ float rE[2][2][T];    // Ericksen xx and yx, rows f-2 .. f-1
-    __shared__ float rV[2][2][T];    // velocity rows f-3 .. f-2
-    __shared__ float rQs[2][3][T];   // predicted stress rows f-4 .. f-3
-    __shared__ double rQp[2][2][T];  // predicted polarization rows f-4 .. f-3
+    constexpr int TP = POL ? T : 1;   // the P rings exist only in the variant with P
+    __shared__ double rP[4][2][TP];   // polarization rows f-3 .. f
+    __shared__ float rS[3][3][T];     // stress rows f-3 .. f-1
+    __shared__ float rE[2][2][TP];    // Ericksen xx and yx, rows f-2 .. f-1
+    __shared__ float rV[2][2][T];     // velocity rows f-3 .. f-2
+    __shared__ float rQs[2][3][T];    // predicted stress rows f-4 .. f-3
+    __shared__ double rQp[2][2][TP];  // predicted polarization rows f-4 .. f-3
     __shared__ float4 sTab[2 * kStiffSeg];     // stiffness cubics of the item's simulation
     __shared__ ItemBody sIB[kItemBodies];      // bodies whose patches touch the item
     __shared__ int sNB;                        // their number, -1 if more than kItemBodies
@@ -584,8 +588,10 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
         Carry carA, carB;
         {
             const unsigned iP = r0 * nx + x, iS = rm1 * nx + x;
-            preA.P0 = ld32(Pi, iP);
-            preA.P1 = ld32(Pi, N + iP);
+            if (POL) {
+                preA.P0 = ld32(Pi, iP);
+                preA.P1 = ld32(Pi, N + iP);
+            }
             preA.S0 = ld32(sgi, iS);
             preA.S1 = ld32(sgi, N + iS);
             preA.S2 = ld32(sgi, 2u * N + iS);
@@ -604,8 +610,10 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             const int o1 = (j + 1) & 1, o0 = j & 1;   // rows f-1 / f-3 (odd lag) and f-2 / f-4 (even lag)
 
             // ---- stage A: commit P(f), sigma(f-1); take this iteration's populations
-            rP[a0][0][tid] = pin.P0;
-            rP[a0][1][tid] = pin.P1;
+            if (POL) {
+                rP[a0][0][tid] = pin.P0;
+                rP[a0][1][tid] = pin.P1;
+            }
             rS[b1][0][tid] = pin.S0;
             rS[b1][1][tid] = pin.S1;
             rS[b1][2][tid] = pin.S2;
@@ -616,8 +624,10 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             // f-1: h_n(x, r) = h*_n(x - c_n, r - c_n) from rows f-2, f-1, f
             if (j + 1 < niter) {
                 const unsigned iP = rp1 * nx + x, iS = r0 * nx + x;
-                pout.P0 = ld32(Pi, iP);
-                pout.P1 = ld32(Pi, N + iP);
+                if (POL) {
+                    pout.P0 = ld32(Pi, iP);
+                    pout.P1 = ld32(Pi, N + iP);
+                }
                 pout.S0 = ld32(sgi, iS);
                 pout.S1 = ld32(sgi, N + iS);
                 pout.S2 = ld32(sgi, 2u * N + iS);
@@ -645,7 +655,7 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             eyy3 = eyy2;
             exy2 = exy1;
             eyy2 = eyy1;
-            if (j >= 2 && colB) {
+            if (POL && j >= 2 && colB) {
                 const int an = walls && rm1 == ytop ? a1 : a0, as = walls && rm1 == 0u ? a1 : a2;
                 double Pc[2] = {rP[a1][0][tid], rP[a1][1][tid]};
                 double Pe[2] = {rP[a1][0][xe ? tid : tid + 1], rP[a1][1][xe ? tid : tid + 1]};
@@ -668,7 +678,7 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                 const int te = xe ? tid : tid + 1, tw = xw ? tid : tid - 1;   // mirror ghosts at x walls
                 float Fx = 0.5f * (rS[b2][0][te] - rS[b2][0][tw]) + 0.5f * (rS[bn][2][tid] - rS[bs][2][tid]);
                 float Fy = 0.5f * (rS[b2][2][te] - rS[b2][2][tw]) + 0.5f * (rS[bn][1][tid] - rS[bs][1][tid]);
-                if (S.ericksen) {
+                if (POL && S.ericksen) {
                     const float exn = chi ? exy2 : exy1, exs = clo ? exy2 : exy3;
                     const float eyn = chi ? eyy2 : eyy1, eys = clo ? eyy2 : eyy3;
                     Fx += 0.5f * (rE[o0][0][te] - rE[o0][0][tw]) + 0.5f * (exn - exs);
@@ -701,7 +711,7 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             if (j >= 5 && colD) {
                 cout.vx = rV[o1][0][tid];
                 cout.vy = rV[o1][1][tid];
-                double Pc[2] = {rP[a3][0][tid], rP[a3][1][tid]};
+                double Pc[2] = {POL ? rP[a3][0][tid] : 0.0, POL ? rP[a3][1][tid] : 0.0};
                 float X[3];
 #pragma unroll
                 for (int q = 0; q < 3; ++q) X[q] = rS[b3][q][tid];
@@ -714,12 +724,8 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                     const float sxe = xe ? -1.0f : 1.0f, sxw = xw ? -1.0f : 1.0f;   // no-slip ghosts
                     cout.g = grad_v(sxe * rV[o1][0][te], sxw * rV[o1][0][tw], vxn, vxs,
                                     sxe * rV[o1][1][te], sxw * rV[o1][1][tw], vyn, vys);
-                    double Pe[2] = {rP[a3][0][te], rP[a3][1][te]};
-                    double Pw[2] = {rP[a3][0][tw], rP[a3][1][tw]};
-                    const int an = dhi ? a3 : a2;
-                    double Pn[2] = {rP[an][0][tid], rP[an][1][tid]};
-                    double Ps[2] = {dlo ? Pc[0] : cin.p0, dlo ? Pc[1] : cin.p1};
-                    cout.k = stiffness(S, sTab, (float)Pc[0], (float)Pc[1]);
+                    // without P: the isotropic stiffness (all anisotropic parts vanish at P = 0)
+                    cout.k = POL ? stiffness(S, sTab, (float)Pc[0], (float)Pc[1]) : Stiff{0.f, 0.f, 0.f, 0.f};
                     float Xe[3], Xw[3], Xn[3], Rs[3];
                     const int bn = dhi ? b3 : b2;
 #pragma unroll
@@ -730,13 +736,20 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                     }
                     const float Xs[3] = {dlo ? X[0] : cin.s0, dlo ? X[1] : cin.s1, dlo ? X[2] : cin.s2};
                     rhs_sigma(S, cout.k, cout.g, cout.vx, cout.vy, X, Xe, Xw, Xn, Xs, Rs);
-                    double Rp[2];
-                    rhs_P(S, cout.g, cout.vx, cout.vy, Pc, Pe, Pw, Pn, Ps, Rp);
                     rQs[o1][0][tid] = X[0] + Rs[0];
                     rQs[o1][1][tid] = X[1] + Rs[1];
                     rQs[o1][2][tid] = X[2] + Rs[2];
-                    rQp[o1][0][tid] = Pc[0] + Rp[0];
-                    rQp[o1][1][tid] = Pc[1] + Rp[1];
+                    if (POL) {
+                        double Pe[2] = {rP[a3][0][te], rP[a3][1][te]};
+                        double Pw[2] = {rP[a3][0][tw], rP[a3][1][tw]};
+                        const int an = dhi ? a3 : a2;
+                        double Pn[2] = {rP[an][0][tid], rP[an][1][tid]};
+                        double Ps[2] = {dlo ? Pc[0] : cin.p0, dlo ? Pc[1] : cin.p1};
+                        double Rp[2];
+                        rhs_P(S, cout.g, cout.vx, cout.vy, Pc, Pe, Pw, Pn, Ps, Rp);
+                        rQp[o1][0][tid] = Pc[0] + Rp[0];
+                        rQp[o1][1][tid] = Pc[1] + Rp[1];
+                    }
                 }
                 cout.s0 = X[0];
                 cout.s1 = X[1];
@@ -753,8 +766,8 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                 double Y[2], Ye[2], Yw[2], Yn[2], Rp[2];
 #pragma unroll
                 for (int q = 0; q < 3; ++q) X[q] = rQs[o0][q][tid];
-                Y[0] = rQp[o0][0][tid];
-                Y[1] = rQp[o0][1][tid];
+                Y[0] = POL ? rQp[o0][0][tid] : 0.0;
+                Y[1] = POL ? rQp[o0][1][tid] : 0.0;
                 if (j >= 8) {
                     const bool elo = walls && rm4 == 0u, ehi = walls && rm4 == ytop;
                     const int on = ehi ? o0 : o1;
@@ -767,20 +780,22 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                     }
                     const float Xs[3] = {elo ? X[0] : cin.q0, elo ? X[1] : cin.q1, elo ? X[2] : cin.q2};
                     rhs_sigma(S, cin.k, cin.g, cin.vx, cin.vy, X, Xe, Xw, Xn, Xs, Rs);
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        Ye[q] = rQp[o0][q][te];
-                        Yw[q] = rQp[o0][q][tw];
-                        Yn[q] = rQp[on][q][tid];
-                    }
-                    const double Ys[2] = {elo ? Y[0] : cin.qp0, elo ? Y[1] : cin.qp1};
-                    rhs_P(S, cin.g, cin.vx, cin.vy, Y, Ye, Yw, Yn, Ys, Rp);
                     const unsigned o = rm4 * nx + x;
                     st32(sgo, o, 0.5f * ((cin.s0 + X[0]) + Rs[0]));
                     st32(sgo, N + o, 0.5f * ((cin.s1 + X[1]) + Rs[1]));
                     st32(sgo, 2u * N + o, 0.5f * ((cin.s2 + X[2]) + Rs[2]));
-                    st32(Po, o, 0.5 * ((cin.p0 + Y[0]) + Rp[0]));
-                    st32(Po, N + o, 0.5 * ((cin.p1 + Y[1]) + Rp[1]));
+                    if (POL) {   // without P both P buffers stay zero
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) {
+                            Ye[q] = rQp[o0][q][te];
+                            Yw[q] = rQp[o0][q][tw];
+                            Yn[q] = rQp[on][q][tid];
+                        }
+                        const double Ys[2] = {elo ? Y[0] : cin.qp0, elo ? Y[1] : cin.qp1};
+                        rhs_P(S, cin.g, cin.vx, cin.vy, Y, Ye, Yw, Yn, Ys, Rp);
+                        st32(Po, o, 0.5 * ((cin.p0 + Y[0]) + Rp[0]));
+                        st32(Po, N + o, 0.5 * ((cin.p1 + Y[1]) + Rp[1]));
+                    }
                 }
                 cout.q0 = X[0];
                 cout.q1 = X[1];
@@ -1237,30 +1252,29 @@ hipError_t launch_ib(bool advance, int nbodies, int ntiles, hipStream_t st, cons
     return hipGetLastError();
 }
 
-// the kernel for (work-group size, storage type, walls)
+// the kernel for (work-group size, storage type, walls, polarization)
 typedef void (*FusedFn)(const SimDev *, const BodyDev *, const WorkItem *, int, int, int *);
-static FusedFn fused_fn(int T, bool fp16, bool walls) {
-    if (T == 128) {
-        if (fp16) return walls ? k_fused<128, __half, true> : k_fused<128, __half, false>;
-        return walls ? k_fused<128, float, true> : k_fused<128, float, false>;
-    }
-    if (T == 256) {
-        if (fp16) return walls ? k_fused<256, __half, true> : k_fused<256, __half, false>;
-        return walls ? k_fused<256, float, true> : k_fused<256, float, false>;
-    }
+template <int T, typename HT>
+static FusedFn fused_fn_t(bool walls, bool pol) {
+    if (walls) return pol ? k_fused<T, HT, true, true> : k_fused<T, HT, true, false>;
+    return pol ? k_fused<T, HT, false, true> : k_fused<T, HT, false, false>;
+}
+static FusedFn fused_fn(int T, bool fp16, bool walls, bool pol) {
+    if (T == 128) return fp16 ? fused_fn_t<128, __half>(walls, pol) : fused_fn_t<128, float>(walls, pol);
+    if (T == 256) return fp16 ? fused_fn_t<256, __half>(walls, pol) : fused_fn_t<256, float>(walls, pol);
     return nullptr;
 }
 
-hipError_t launch_fused(int T, bool fp16, bool walls, int grid, hipStream_t st, const SimDev *sims,
+hipError_t launch_fused(int T, bool fp16, bool walls, bool pol, int grid, hipStream_t st, const SimDev *sims,
                         const BodyDev *bodies, const WorkItem *items, int n_items, int cur, int *d_t) {
-    FusedFn f = fused_fn(T, fp16, walls);
+    FusedFn f = fused_fn(T, fp16, walls, pol);
     if (!f) return hipErrorInvalidValue;
     hipLaunchKernelGGL(f, dim3(grid), dim3(T), 0, st, sims, bodies, items, n_items, cur, d_t);
     return hipGetLastError();
 }
 
-int fused_blocks_per_cu(int T, bool fp16, bool walls) {
-    FusedFn f = fused_fn(T, fp16, walls);
+int fused_blocks_per_cu(int T, bool fp16, bool walls, bool pol) {
+    FusedFn f = fused_fn(T, fp16, walls, pol);
     int n = 0;
     hipError_t e = f ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, T, 0) : hipErrorInvalidValue;
     return e == hipSuccess && n > 0 ? n : 1;

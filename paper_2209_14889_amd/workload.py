@@ -246,4 +246,40 @@ def return_of(com_x0: float, com_x_end: float, d_pull: float) -> float:
     return 1.0 - abs(com_x_end - com_x0) / d_pull
 
 
+# The paper's own parameters (Tables I-IV) in lattice units of its unit map: dx = 4e-8 m,
+# dt = 8e-6 s, rho_s = 2e7 kg/m^3, so stress 500 Pa, viscosity 4e-3 Pa s, diffusivity
+# 2e-10 m^2/s, stiffness (N/m) 2e-5, energy 3.2e-20 J, length 4e-8 m, time 8e-6 s.
+PAPER_STEPS = 187_500
+PAPER_UNITS = dict(stress=500.0, viscosity=4e-3, diffusivity=2e-10, stiffness=2e-5, energy=3.2e-20, length=4e-8,
+                   time=8e-6)
+
+
+def paper_case(D_p: float = 1e-13, radius_m: float = 5e-7, T_pull_s: float = 0.2, d_pull_m: float = 4e-6,
+               theta0: float = 0.0, alpha: float = -0.9, n: int = 250) -> Workload:
+    """The paper's experiment at its own size (Tables I-IV, App. C): a 250 x 250 closed box, tau 1.25,
+    a droplet of radius 0.5 um (12.5 sites, nodes 0.5 sites apart) dragged 4 um (100 sites) over
+    0.2 s (25 000 steps) by the trap and let go, 187 500 steps in all; stress-related values
+    divided by the 500 Pa stress unit.  Physical inputs in SI units, converted here."""
+    U = PAPER_UNITS
+    Kx = tuple(v / U["stress"] for v in (0.01, 0.005, 0.005, 0.005))
+    params = dict(tau=1.25, Kx=Kx, eta_p=0.1 / U["viscosity"], D_p=D_p / U["diffusivity"], P_clamp=0.99, ericksen=1,
+                  xi=1.1, alpha=alpha, beta=1.0, kappa=0.001, Gamma=1.0, walls=2)
+    P_eq = math.sqrt(max(0.0, -alpha))
+    P0 = director_field(np.full((n, n), theta0), P_eq)
+    R = radius_m / U["length"]
+    l_eq = 2e-8 / U["length"]
+    nn = int(round(2 * math.pi * R / l_eq))
+    d_pull = d_pull_m / U["length"]
+    T_pull = T_pull_s / U["time"]
+    x0 = n / 2 - d_pull / 2
+    body = make_body(x0, n / 2, R, nn, (0.0, 0.0), k_spring=1e-5 / U["stiffness"])
+    body.eps_angle = 1e-20 / U["energy"]
+    c = body.R.mean(axis=0)
+    t1 = 30.0 + 3 * 30.0
+    body.trap = dict(k=1e-6 / U["stiffness"], x0=float(c[0]), y0=float(c[1]), dx=float(d_pull), dy=0.0, t1=t1,
+                     t2=t1 + T_pull, w=30.0)
+    return Workload("paper", [SimSpec(n, n, params, P0, [body], meta=dict(d_pull=d_pull))], PAPER_STEPS, "fp32",
+                    dict(d_pull=d_pull, T_pull=T_pull))
+
+
 WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4}

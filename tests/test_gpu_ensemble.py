@@ -69,3 +69,41 @@ def test_body_update_paths_agree():
             assert np.array_equal(a[k], b[k]), (i, k)
         assert np.array_equal(ens.nodes(i)[0], one.nodes(0)[0]), i
         one.close()
+
+
+def test_scalar_variant_matches_tensorial_path():
+    """With P = 0 in every simulation the field kernel runs its variant without the polarization
+    work (the scalar model, Sec. II B).  At P = 0 the tensorial arithmetic reduces to the same
+    operations plus exact zeros (Ericksen stress, anisotropic stiffness), so a P = 0 simulation
+    alone (scalar variant) and batched with a polarized one (tensorial variant) agree to FP32
+    rounding (the compiler may fuse multiply-adds differently in the two instantiations)."""
+    scalar = wl.trap_case(52, 72, 56, k_trap=0.5, walls=2, P_eq=0.0).sims[0]
+    polar = wl.small_case(53, 64, 48).sims[0]
+    say("case scalar variant vs tensorial path, 72x56 box trap + 64x48 polarized, 300 steps")
+    one = lb.Sim([scalar], lb.make_options(seg_rows=8))
+    both = lb.Sim([scalar, polar], lb.make_options(seg_rows=8))
+    one.step(300)
+    both.step(300)
+    a, b = one.fields(0), both.fields(0)
+    for k in ("vx", "vy", "sxx", "syy", "sxy"):
+        e = linf_rel(a[k], b[k])
+        say(f"  {k} {e:.1e}")
+        assert e <= 1e-6, k
+    assert np.max(np.abs(a["rho"] - b["rho"])) <= 1e-6
+    assert np.all(a["Px"] == 0) and np.all(a["Py"] == 0) and np.all(b["Px"] == 0)
+    assert np.max(np.abs(one.nodes(0)[0] - both.nodes(0)[0])) <= 1e-7
+
+
+def test_scalar_variant_matches_oracle():
+    w = wl.trap_case(54, 64, 48, k_trap=0.5, walls=2, P_eq=0.0)
+    say("case scalar variant vs oracle, 64x48 box trap, 600 steps")
+    g = lb.Sim(w, lb.make_options(seg_rows=12))
+    r = oracle_sim(w.sims[0])
+    g.step(600)
+    r.run(600)
+    gf, of = g.fields(), r.observe()
+    for k in ("vx", "vy", "sxx", "syy", "sxy"):
+        e = linf_rel(gf[k], of[k])
+        say(f"  {k} {e:.2e}")
+        assert e <= 1e-4, k
+    assert np.max(np.abs(g.nodes()[0] - r.bodies[0].R)) <= 1e-5

@@ -118,3 +118,20 @@ def test_box_trap_parity(kernel):
         for k, e in errs.items():
             assert e <= 1e-4, (k, e)
         assert np.max(np.abs(g.nodes()[0] - r.bodies[0].R)) <= 1e-5
+
+
+def test_paper_case_parity():
+    """The paper's own configuration (Tables I-IV in its lattice units: 250^2 closed box, tau 1.25,
+    157-node droplet, trap 0.05) for the first 400 steps, through the trap's switch-on."""
+    w = wl.paper_case()
+    say("case paper 250x250 box, 400 steps")
+    g = lb.Sim(w, lb.make_options(graph_chunk=100))
+    r = oracle_sim(w.sims[0])
+    g.step(400)
+    r.run(400)
+    gf, of = g.fields(), r.observe()
+    errs = {k: linf_rel(gf[k], of[k]) for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py")}
+    say("  ", {k: f"{v:.1e}" for k, v in errs.items()})
+    for k, e in errs.items():
+        assert e <= 1e-4, (k, e)
+    assert np.max(np.abs(g.nodes()[0] - r.bodies[0].R)) <= 1e-5
