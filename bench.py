@@ -66,6 +66,10 @@ def workload(name: str, steps: int):
         w = wl.paper_case()
         return w, ("the paper's experiment (Tables I-IV): 250x250 closed box, tau 1.25, 157-node droplet dragged 100 "
                    "sites over 25000 steps by the trap, 187500 steps"), 0
+    if name == "paper_scalar":
+        w = wl.paper_case(scalar=True)
+        return w, ("the paper's experiment with the scalar model (Sec. II B, C = 0.01 Pa): 250x250 closed box, "
+                   "157-node droplet dragged 100 sites over 25000 steps by the trap, 187500 steps"), 0
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -259,27 +263,52 @@ def main():
     sim = lb.Sim(w, opt)
     shape = sim.launch_shape()
     log(f"bench: fused launch shape {shape}")
+    paper = args.workload.startswith("paper")
+    failure = None
     sim.step(args.warmup)
     sim.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step(args.steps)
-    sim.sync()
+    if paper:
+        # the whole protocol in chunks, so a watchdog stop is reported with the step it came at
+        done = 0
+        while done < args.steps and failure is None:
+            n = min(12500, args.steps - done)
+            try:
+                sim.step(n)
+                sim.sync()
+            except lb.LBError as e:
+                failure = f"stopped at step {sim.t}: {e}"
+                break
+            done += n
+            log(f"bench: {args.warmup + done} steps")
+    else:
+        sim.step(args.steps)
+        sim.sync()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     mlups = sites * args.steps / dt / 1e6
     log(f"bench: {args.steps} steps in {dt:.4f} s -> {mlups:.1f} MLUPS")
     experiment = None
-    if args.workload == "paper":
+    if paper:
         # the droplet's Return (Sec. III) once the whole protocol has run
         b0 = w.sims[0].bodies[0]
-        com = sim.body_forces()[0, 4:6]
         total = args.warmup + args.steps
-        ret = wl_mod.return_of(b0.trap["x0"], com[0], b0.trap["dx"]) if total >= wl_mod.PAPER_STEPS else None
-        experiment = {"steps": total, "timed_s": round(dt, 3), "return": None if ret is None else round(ret, 4),
-                      "final_com": [round(float(c), 4) for c in com],
-                      "paper_cpu_wall": "about 20 h for 187500 steps on one CPU core (App. C)"}
+        if failure is None:
+            com = sim.body_forces()[0, 4:6]
+            from paper_2209_14889_amd.experiment import return_value
+            ret = (return_value((b0.trap["x0"], b0.trap["y0"]), com, b0.trap["dx"])
+                   if total >= wl_mod.PAPER_STEPS else None)
+            experiment = {"steps": total, "timed_s": round(dt, 3), "return": None if ret is None else round(ret, 4),
+                          "final_com": [round(float(c), 4) for c in com]}
+        else:
+            experiment = {"steps": total, "timed_s": round(dt, 3), "return": None, "failure": failure}
+        experiment["paper_cpu_wall"] = ("about 4 h for 187500 steps of the scalar model on one CPU (App. C)"
+                                        if args.workload == "paper_scalar" else
+                                        "about 20 h for 187500 steps on one CPU (App. C)")
         log(f"bench: paper experiment {experiment}")
+        if failure is not None:
+            mlups = sites * done / dt / 1e6
     sim.close()
 
     # roofline of the dominant kernel: HIP events around every field-kernel launch on the

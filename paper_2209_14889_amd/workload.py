@@ -240,12 +240,6 @@ def trap_case(seed: int, nx: int, ny: int, radius: float = 6.0, d_pull: float = 
                     dict(d_pull=d_pull, T_pull=T_pull))
 
 
-def return_of(com_x0: float, com_x_end: float, d_pull: float) -> float:
-    """Return = 1 - d_rec / d_pull (Sec. III), d_rec the distance of the final centre of mass from
-    the initial one."""
-    return 1.0 - abs(com_x_end - com_x0) / d_pull
-
-
 # The paper's own parameters (Tables I-IV) in lattice units of its unit map: dx = 4e-8 m,
 # dt = 8e-6 s, rho_s = 2e7 kg/m^3, so stress 500 Pa, viscosity 4e-3 Pa s, diffusivity
 # 2e-10 m^2/s, stiffness (N/m) 2e-5, energy 3.2e-20 J, length 4e-8 m, time 8e-6 s.
@@ -255,16 +249,39 @@ PAPER_UNITS = dict(stress=500.0, viscosity=4e-3, diffusivity=2e-10, stiffness=2e
 
 
 def paper_case(D_p: float = 1e-13, radius_m: float = 5e-7, T_pull_s: float = 0.2, d_pull_m: float = 4e-6,
-               theta0: float = 0.0, alpha: float = -0.9, n: int = 250) -> Workload:
+               theta0: float = 0.0, alpha: float = -0.9, n: int = 250, scalar: bool = False,
+               fe_units: str = "Pa") -> Workload:
     """The paper's experiment at its own size (Tables I-IV, App. C): a 250 x 250 closed box, tau 1.25,
     a droplet of radius 0.5 um (12.5 sites, nodes 0.5 sites apart) dragged 4 um (100 sites) over
     0.2 s (25 000 steps) by the trap and let go, 187 500 steps in all; stress-related values
-    divided by the 500 Pa stress unit.  Physical inputs in SI units, converted here."""
+    divided by the 500 Pa stress unit.  Physical inputs in SI units, converted here.
+
+    scalar=True gives the scalar model of Sec. II B (eqMaxDiff, C = 0.01 Pa of Table IV): no
+    polarization, and an isotropic K^x = (C, 0, C, C/2), for which the stiffness operator is C times
+    the identity on (Xxx, Xyy, Xxy) whatever P is, so the tensorial step reduces exactly to
+    C Psi - (C / eta_p) sigma + D_p lap sigma.
+
+    fe_units: the unit of the free-energy coefficients alpha, beta, kappa (Table III prints no unit).
+    "Pa" (default) converts them with the 500 Pa stress unit like every other stress in Tables I-IV
+    (alpha = -0.9 -> -1.8e-3, beta 2e-3, kappa 2e-6), which keeps |P|_eq = sqrt(-alpha / beta) and
+    the quasi-static flow-alignment viscosity xi^2 |P|^2 / Gamma and puts the magnitude relaxation at
+    1 / (2 Gamma beta |P|^2) = 280 steps.  "lattice" takes the printed numbers as lattice units, where
+    that relaxation takes 0.55 steps and the coupled flow-magnitude response carries waves faster than
+    one site per step: the explicit step then grows a grid-scale mode at the walls and the protocol
+    stops after 5 000 - 45 000 steps for every alpha != 0."""
     U = PAPER_UNITS
-    Kx = tuple(v / U["stress"] for v in (0.01, 0.005, 0.005, 0.005))
-    params = dict(tau=1.25, Kx=Kx, eta_p=0.1 / U["viscosity"], D_p=D_p / U["diffusivity"], P_clamp=0.99, ericksen=1,
-                  xi=1.1, alpha=alpha, beta=1.0, kappa=0.001, Gamma=1.0, walls=2)
-    P_eq = math.sqrt(max(0.0, -alpha))
+    if scalar:
+        C = 0.01 / U["stress"]
+        Kx = (C, 0.0, C, 0.5 * C)
+    else:
+        Kx = tuple(v / U["stress"] for v in (0.01, 0.005, 0.005, 0.005))
+    if fe_units not in ("Pa", "lattice"):
+        raise ValueError("fe_units must be 'Pa' or 'lattice'")
+    fe = U["stress"] if fe_units == "Pa" else 1.0
+    params = dict(tau=1.25, Kx=Kx, eta_p=0.1 / U["viscosity"], D_p=D_p / U["diffusivity"], P_clamp=0.99,
+                  ericksen=0 if scalar else 1, xi=1.1, alpha=alpha / fe, beta=1.0 / fe, kappa=0.001 / fe,
+                  Gamma=1.0, walls=2)
+    P_eq = 0.0 if scalar else math.sqrt(max(0.0, -alpha))
     P0 = director_field(np.full((n, n), theta0), P_eq)
     R = radius_m / U["length"]
     l_eq = 2e-8 / U["length"]
@@ -278,7 +295,8 @@ def paper_case(D_p: float = 1e-13, radius_m: float = 5e-7, T_pull_s: float = 0.2
     t1 = 30.0 + 3 * 30.0
     body.trap = dict(k=1e-6 / U["stiffness"], x0=float(c[0]), y0=float(c[1]), dx=float(d_pull), dy=0.0, t1=t1,
                      t2=t1 + T_pull, w=30.0)
-    return Workload("paper", [SimSpec(n, n, params, P0, [body], meta=dict(d_pull=d_pull))], PAPER_STEPS, "fp32",
+    return Workload("paper_scalar" if scalar else "paper", [SimSpec(n, n, params, P0, [body], meta=dict(d_pull=d_pull))],
+                    PAPER_STEPS, "fp32",
                     dict(d_pull=d_pull, T_pull=T_pull))
 
 

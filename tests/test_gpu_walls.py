@@ -120,11 +120,13 @@ def test_box_trap_parity(kernel):
         assert np.max(np.abs(g.nodes()[0] - r.bodies[0].R)) <= 1e-5
 
 
-def test_paper_case_parity():
+@pytest.mark.parametrize("fe_units", ["Pa", "lattice"])
+def test_paper_case_parity(fe_units):
     """The paper's own configuration (Tables I-IV in its lattice units: 250^2 closed box, tau 1.25,
-    157-node droplet, trap 0.05) for the first 400 steps, through the trap's switch-on."""
-    w = wl.paper_case()
-    say("case paper 250x250 box, 400 steps")
+    157-node droplet, trap 0.05) for the first 400 steps, through the trap's switch-on, with the
+    free-energy coefficients read in either unit."""
+    w = wl.paper_case(fe_units=fe_units)
+    say(f"case paper 250x250 box fe_units={fe_units}, 400 steps")
     g = lb.Sim(w, lb.make_options(graph_chunk=100))
     r = oracle_sim(w.sims[0])
     g.step(400)
@@ -134,4 +136,23 @@ def test_paper_case_parity():
     say("  ", {k: f"{v:.1e}" for k, v in errs.items()})
     for k, e in errs.items():
         assert e <= 1e-4, (k, e)
+    assert np.max(np.abs(g.nodes()[0] - r.bodies[0].R)) <= 1e-5
+
+
+def test_paper_scalar_case_parity():
+    """The same experiment with the scalar model (Sec. II B, C = 0.01 Pa): no polarization, so the
+    library runs its scalar kernel variant; 600 steps through the trap's switch-on and the start of
+    the drag."""
+    w = wl.paper_case(scalar=True)
+    say("case paper scalar model 250x250 box, 600 steps")
+    g = lb.Sim(w, lb.make_options(graph_chunk=100))
+    r = oracle_sim(w.sims[0])
+    g.step(600)
+    r.run(600)
+    gf, of = g.fields(), r.observe()
+    errs = {k: linf_rel(gf[k], of[k]) for k in ("vx", "vy", "sxx", "syy", "sxy")}
+    say("  ", {k: f"{v:.1e}" for k, v in errs.items()})
+    for k, e in errs.items():
+        assert e <= 1e-4, (k, e)
+    assert np.all(gf["Px"] == 0.0) and np.all(gf["Py"] == 0.0)
     assert np.max(np.abs(g.nodes()[0] - r.bodies[0].R)) <= 1e-5

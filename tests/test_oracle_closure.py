@@ -111,6 +111,11 @@ def test_scalar_limit_recovers_scalar_modulus():
     Kmod = 0.02
     C = oracle.stiffness(0.0, 0.0, (Kmod, 0.0, Kmod, Kmod / 2))
     assert np.allclose(C, Kmod * np.eye(3), atol=1e-17)
+    # K^x itself isotropic: every rotation of it is the same tensor, so any orientation
+    # distribution averages to it and the scalar model of Sec. II B holds at every P
+    for P, th in ((0.5, 0.3), (0.9, 2.0), (0.99, -1.1)):
+        C = oracle.stiffness(P * math.cos(th), P * math.sin(th), (Kmod, 0.0, Kmod, Kmod / 2))
+        assert np.allclose(C, Kmod * np.eye(3), rtol=0, atol=1e-16), (P, th, C)
 
 
 def test_strong_alignment_tends_to_kx():
