@@ -101,9 +101,10 @@ def test_trap_protocol_parity(walls):
 @pytest.mark.parametrize("kernel", [0, 1], ids=["fused", "multipass"])
 def test_box_trap_parity(kernel):
     """The closed box (walls on all four sides) with the trap protocol and a polarized director along
-    the pull, against the oracle through the pull and the release.  (With the director oblique to
-    the walls the Ericksen coupling makes the box corners unstable in the oracle itself, so the
-    FP32 and FP64 runs part ways; that case is exercised in the channel instead.)"""
+    the pull, against the oracle through the pull and the release.  (Free-energy coefficients in
+    lattice units with the director oblique to the walls grow a grid-scale wall mode from round-off
+    in the oracle itself, so the FP32 and FP64 runs part ways; that case is exercised in the channel
+    instead.)"""
     w = wl.trap_case(51, 60, 44, radius=6.0, d_pull=4.0, T_pull=400.0, k_trap=0.5, walls=2, P_eq=0.9,
                      theta0=0.0)
     say(f"case box trap kernel={kernel} 60x44 seed=51 steps 300/600/900")
