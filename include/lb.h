@@ -100,7 +100,7 @@ typedef struct {
     int32_t kernel;             /* 0: fused single-pass field kernel; 1: multi-pass kernels */
     int32_t timing;             /* 1: time every field-kernel launch with HIP events */
     int32_t seg_rows;           /* rows per fused work item; 0 = tuned default */
-    int32_t fused_threads;      /* fused work-group size: 128 or 256 (strip of 120 or 248
+    int32_t fused_threads;      /* fused work-group size: 64, 128 or 256 (strip of 56, 120 or 248
                                    columns); 0 = chosen from the lattice width */
     int32_t autotune;           /* 1: time candidate (work-group size, rows per item, grid) shapes on
                                    the live state in lb_create and keep the fastest; 0: cost model */

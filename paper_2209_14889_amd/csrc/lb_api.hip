@@ -239,7 +239,8 @@ int validate(const lb_sim_params *sims, int n_sims, const Opt &o) {
     if (o.shift < 0 || o.shift > 24) return fail(LB_EINVAL, "fp16_shift out of range");
     if (o.kernel != 0 && o.kernel != 1) return fail(LB_EINVAL, "kernel must be 0 or 1");
     if (o.chunk < 0 || (o.chunk & 1)) return fail(LB_EINVAL, "graph_chunk must be even and >= 0");
-    if (o.threads != 0 && o.threads != 128 && o.threads != 256) return fail(LB_EINVAL, "fused_threads must be 0, 128 or 256");
+    if (o.threads != 0 && o.threads != 64 && o.threads != 128 && o.threads != 256)
+        return fail(LB_EINVAL, "fused_threads must be 0, 64, 128 or 256");
     if (o.seg < 0) return fail(LB_EINVAL, "seg_rows must be >= 0");
     if (o.grid < 0) return fail(LB_EINVAL, "grid must be >= 0");
     for (int s = 0; s < n_sims; ++s) {
@@ -364,7 +365,7 @@ Plan make_plan(const lb_sim_params *sims, int n_sims, const Opt &o) {
     // the shortest segments any choice may use
     size_t max_items = 0;
     for (int s = 0; s < n_sims; ++s) {
-        int W = 128 - 2 * kHalo;
+        int W = 64 - 2 * kHalo;   // the narrowest strips any work-group size uses
         max_items += (size_t)((sims[s].nx + W - 1) / W) * (size_t)((sims[s].ny + 3) / 4);
     }
     pl.items.resize(max_items);
@@ -599,7 +600,7 @@ int choose_fused_config(lb_handle *h) {
         bool operator==(const Cand &o) const { return T == o.T && seg == o.seg && grid == o.grid; }
     };
     std::vector<Cand> cand;
-    for (int T : {128, 256}) {
+    for (int T : {64, 128, 256}) {
         if (h->opt.threads && T != h->opt.threads) continue;
         int slots = cus * fused_blocks_per_cu(T, fp16, h->any_walls, h->any_pol);
         int m = model_seg(h->plan.sims, T, slots);

@@ -1260,6 +1260,7 @@ static FusedFn fused_fn_t(bool walls, bool pol) {
     return pol ? k_fused<T, HT, false, true> : k_fused<T, HT, false, false>;
 }
 static FusedFn fused_fn(int T, bool fp16, bool walls, bool pol) {
+    if (T == 64) return fp16 ? fused_fn_t<64, __half>(walls, pol) : fused_fn_t<64, float>(walls, pol);
     if (T == 128) return fp16 ? fused_fn_t<128, __half>(walls, pol) : fused_fn_t<128, float>(walls, pol);
     if (T == 256) return fp16 ? fused_fn_t<256, __half>(walls, pol) : fused_fn_t<256, float>(walls, pol);
     return nullptr;
