@@ -174,6 +174,27 @@ def trace_summary(db: str, title: str, command: str, out: str, top: int = 8):
     log(f"bench: wrote profiles/{out}")
 
 
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """GB/s (bytes read + bytes written) of a device-to-device copy of nbytes, best of reps."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    best = 1e30
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / best / 1e9
+
+
 def cpu_baseline(w, name: str, budget_s: float = 15.0):
     """FP64 oracle on the host: the full coupled step on the workload's first simulation for as
     many steps as fit in about budget_s seconds (at least 2)."""
@@ -329,6 +350,10 @@ def main():
     log(f"bench: field kernel {avg_ms * 1e3:.2f} us/launch, body kernel {ib_ms * 1e3:.2f} us/launch, "
         f"{achieved:.0f} GB/s algorithmic")
 
+    # the achievable streaming bandwidth on this device, for context: a 1 GiB device-to-device copy
+    copy_gbps = copy_bandwidth()
+    log(f"bench: device copy {copy_gbps:.0f} GB/s (read + write)")
+
     sur = None
     if not args.no_surrogate:
         from paper_2209_14889_amd import surrogate
@@ -364,7 +389,8 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": counted_traffic(args.workload, shape),
                      "traffic_unit": "GB per launch", "algorithmic_gb_per_launch": round(bps * sites / 1e9, 4),
-                     "kernel": "k_fused", "bytes_per_site": bps, "launch_us": round(avg_ms * 1e3, 3)},
+                     "kernel": "k_fused", "bytes_per_site": bps, "launch_us": round(avg_ms * 1e3, 3),
+                     "copy_gbps": round(copy_gbps, 1), "frac_of_copy": round(achieved / copy_gbps, 4)},
         "cpu_baseline": cpu,
         "surrogate": sur,
     }
