@@ -157,3 +157,24 @@ def test_paper_scalar_case_parity():
         assert e <= 1e-4, (k, e)
     assert np.all(gf["Px"] == 0.0) and np.all(gf["Py"] == 0.0)
     assert np.max(np.abs(g.nodes()[0] - r.bodies[0].R)) <= 1e-5
+
+
+def test_paper_case_parity_4000_steps():
+    """The paper's configuration for 4000 steps: the trap's switch-on and the first sixth of the
+    drag (the droplet moves about 14 sites), fields and nodes against the oracle."""
+    w = wl.paper_case()
+    say("case paper 250x250 box, 4000 steps")
+    g = lb.Sim(w, lb.make_options(graph_chunk=100))
+    r = oracle_sim(w.sims[0])
+    for n in (2000, 2000):
+        g.step(n)
+        r.run(n)
+        gf, of = g.fields(), r.observe()
+        errs = {k: linf_rel(gf[k], of[k]) for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py")}
+        say(f" t={r.t}", {k: f"{v:.1e}" for k, v in errs.items()})
+        for k, e in errs.items():
+            assert e <= 1e-4, (k, e)
+        assert np.max(np.abs(g.nodes()[0] - r.bodies[0].R)) <= 1e-4
+    moved = r.bodies[0].R[:, 0].mean() - w.sims[0].bodies[0].R[:, 0].mean()
+    say(f"  droplet moved {moved:.2f} sites")
+    assert moved > 5.0
