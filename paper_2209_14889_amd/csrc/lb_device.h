@@ -198,45 +198,67 @@ __device__ __forceinline__ void rhs_sigma(const SimDev &S, const Stiff &k, const
     }
 }
 
+// The polarization is FP64 state.  Its right-hand side and the Ericksen stress take the
+// cancelling quantities in FP64 (the slope a = alpha + beta |Y|^2, a small difference of O(1)
+// numbers near the equilibrium magnitude, and the neighbour-minus-centre differences) and the
+// rest in FP32: rounding the values themselves to FP32 would leave a fixed grid-scale pattern of
+// 3e-8 whose Laplacian, through kappa and the Ericksen stress, drives a spurious flow.
+struct PLocal {
+    float c[2];      // centre
+    float d[4][2];   // e, w, n, s minus the centre
+    float a;         // alpha + beta |Y|^2
+};
+__device__ __forceinline__ PLocal p_local(const SimDev &S, const double Y[2], const double Ye[2], const double Yw[2],
+                                          const double Yn[2], const double Ys[2]) {
+    PLocal L;
+    L.a = (float)((double)S.alpha + (double)S.beta * (Y[0] * Y[0] + Y[1] * Y[1]));
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        L.c[q] = (float)Y[q];
+        L.d[0][q] = (float)(Ye[q] - Y[q]);
+        L.d[1][q] = (float)(Yw[q] - Y[q]);
+        L.d[2][q] = (float)(Yn[q] - Y[q]);
+        L.d[3][q] = (float)(Ys[q] - Y[q]);
+    }
+    return L;
+}
+
 // right-hand side of eqBE: -(v.grad)Y - Omega Y + xi Psi Y - Gamma h(Y),
-// h = (alpha + beta |Y|^2) Y - kappa lap Y.  FP64: near the equilibrium magnitude the factor
-// alpha + beta |Y|^2 is a small difference of O(1) numbers, and per-step increments of Y are far
-// below the FP32 resolution of |Y|.
+// h = (alpha + beta |Y|^2) Y - kappa lap Y.  The state Y and the Heun sums stay FP64 (per-step
+// increments of Y are far below the FP32 resolution of |Y|).
 __device__ __forceinline__ void rhs_P(const SimDev &S, const Grad &g, float ux, float uy,
                                       const double Y[2], const double Ye[2], const double Yw[2],
                                       const double Yn[2], const double Ys[2], double R[2]) {
-    const double a = (double)S.alpha + (double)S.beta * (Y[0] * Y[0] + Y[1] * Y[1]);
-    const double kap = S.kappa, xi = S.xi, Gam = S.Gamma;
-    const double om = g.om, p0 = g.psi0, p1 = g.psi1, p2 = g.psi2, vx = ux, vy = uy;
-    double lap0 = ((Ye[0] + Yw[0]) + (Yn[0] + Ys[0])) - 4.0 * Y[0];
-    double lap1 = ((Ye[1] + Yw[1]) + (Yn[1] + Ys[1])) - 4.0 * Y[1];
-    double h0 = a * Y[0] - kap * lap0;
-    double h1 = a * Y[1] - kap * lap1;
-    double adv0 = vx * (0.5 * (Ye[0] - Yw[0])) + vy * (0.5 * (Yn[0] - Ys[0]));
-    double adv1 = vx * (0.5 * (Ye[1] - Yw[1])) + vy * (0.5 * (Yn[1] - Ys[1]));
-    R[0] = -adv0 - om * Y[1] + xi * (p0 * Y[0] + p2 * Y[1]) - Gam * h0;
-    R[1] = -adv1 + om * Y[0] + xi * (p2 * Y[0] + p1 * Y[1]) - Gam * h1;
+    const PLocal L = p_local(S, Y, Ye, Yw, Yn, Ys);
+    const float lap0 = (L.d[0][0] + L.d[1][0]) + (L.d[2][0] + L.d[3][0]);
+    const float lap1 = (L.d[0][1] + L.d[1][1]) + (L.d[2][1] + L.d[3][1]);
+    const float h0 = L.a * L.c[0] - S.kappa * lap0;
+    const float h1 = L.a * L.c[1] - S.kappa * lap1;
+    const float adv0 = ux * (0.5f * (L.d[0][0] - L.d[1][0])) + uy * (0.5f * (L.d[2][0] - L.d[3][0]));
+    const float adv1 = ux * (0.5f * (L.d[0][1] - L.d[1][1])) + uy * (0.5f * (L.d[2][1] - L.d[3][1]));
+    R[0] = (double)(-adv0 - g.om * L.c[1] + S.xi * (g.psi0 * L.c[0] + g.psi2 * L.c[1]) - S.Gamma * h0);
+    R[1] = (double)(-adv1 + g.om * L.c[0] + S.xi * (g.psi2 * L.c[0] + g.psi1 * L.c[1]) - S.Gamma * h1);
 }
 
 // Ericksen stress at a site (Sec. II C 1, with kappa on the gradient term), from FP64 P:
 // out = (xx, xy, yx, yy)
 __device__ __forceinline__ void ericksen(const SimDev &S, const double P[2], const double Pe[2], const double Pw[2],
                                          const double Pn[2], const double Ps[2], float E[4]) {
-    const double a = (double)S.alpha + (double)S.beta * (P[0] * P[0] + P[1] * P[1]);
-    const double kap = S.kappa, xi = S.xi;
-    double lap0 = ((Pe[0] + Pw[0]) + (Pn[0] + Ps[0])) - 4.0 * P[0];
-    double lap1 = ((Pe[1] + Pw[1]) + (Pn[1] + Ps[1])) - 4.0 * P[1];
-    double hx = a * P[0] - kap * lap0;
-    double hy = a * P[1] - kap * lap1;
-    double dxPx = 0.5 * (Pe[0] - Pw[0]), dyPx = 0.5 * (Pn[0] - Ps[0]);
-    double dxPy = 0.5 * (Pe[1] - Pw[1]), dyPy = 0.5 * (Pn[1] - Ps[1]);
-    double anti = -0.5 * (P[0] * hy - hx * P[1]);
-    double sym = 0.5 * xi * (P[0] * hy + hx * P[1]);
-    double gxy = kap * (dxPx * dyPx + dxPy * dyPy);
-    E[0] = (float)(xi * P[0] * hx - kap * (dxPx * dxPx + dxPy * dxPy));
-    E[1] = (float)(anti + sym - gxy);
-    E[2] = (float)(-anti + sym - gxy);
-    E[3] = (float)(xi * P[1] * hy - kap * (dyPx * dyPx + dyPy * dyPy));
+    const PLocal L = p_local(S, P, Pe, Pw, Pn, Ps);
+    const float kap = S.kappa, xi = S.xi, P0 = L.c[0], P1 = L.c[1];
+    const float lap0 = (L.d[0][0] + L.d[1][0]) + (L.d[2][0] + L.d[3][0]);
+    const float lap1 = (L.d[0][1] + L.d[1][1]) + (L.d[2][1] + L.d[3][1]);
+    const float hx = L.a * P0 - kap * lap0;
+    const float hy = L.a * P1 - kap * lap1;
+    const float dxPx = 0.5f * (L.d[0][0] - L.d[1][0]), dyPx = 0.5f * (L.d[2][0] - L.d[3][0]);
+    const float dxPy = 0.5f * (L.d[0][1] - L.d[1][1]), dyPy = 0.5f * (L.d[2][1] - L.d[3][1]);
+    const float anti = -0.5f * (P0 * hy - hx * P1);
+    const float sym = 0.5f * xi * (P0 * hy + hx * P1);
+    const float gxy = kap * (dxPx * dyPx + dxPy * dyPy);
+    E[0] = xi * P0 * hx - kap * (dxPx * dxPx + dxPy * dxPy);
+    E[1] = anti + sym - gxy;
+    E[2] = -anti + sym - gxy;
+    E[3] = xi * P1 * hy - kap * (dyPx * dyPx + dyPy * dyPy);
 }
 
 // (x - o) mod n for |x - o| < 2n, without an integer division
