@@ -53,6 +53,10 @@ template <> struct Pop<float> {
     static __device__ __forceinline__ void store(float *p, size_t i, float v, float) { p[i] = v; }
     static __device__ __forceinline__ float ld(const float *p, unsigned i, float) { return *at32(p, i); }
     static __device__ __forceinline__ void st(float *p, unsigned i, float v, float) { *at32(p, i) = v; }
+    // the stored value as is (for FP16 storage: still times the 2^S scale)
+    static __device__ __forceinline__ float cvt_stored(Raw r) { return r; }
+    static __device__ __forceinline__ void st_stored(float *p, unsigned i, float v) { *at32(p, i) = v; }
+    static constexpr bool kScaled = false;
 };
 template <> struct Pop<__half> {
     // a 32-bit word per value: 16-bit values would be packed in pairs, which waits for both loads
@@ -75,18 +79,34 @@ template <> struct Pop<__half> {
     static __device__ __forceinline__ void st(__half *p, unsigned i, float v, float scale) {
         *at32(reinterpret_cast<unsigned short *>(p), i) = __half_as_ushort(__float2half_rn(v * scale));
     }
+    static __device__ __forceinline__ float cvt_stored(Raw r) { return __half2float(__ushort_as_half((unsigned short)r)); }
+    static __device__ __forceinline__ void st_stored(__half *p, unsigned i, float v) {
+        *at32(reinterpret_cast<unsigned short *>(p), i) = __half_as_ushort(__float2half_rn(v));
+    }
+    static constexpr bool kScaled = true;
 };
 
 // ---- BGK collision with Guo forcing (eqBGK, Sec. II B force coupling) --------------------
 // In: pre-collision offsets d[9], force F.  Out: post-collision offsets in d, and the
-// force-corrected velocity u = (sum c h + F/2)/rho, drho = rho - 1.
-__device__ __forceinline__ void collide(float d[9], float Fx, float Fy, float omega, float guo,
-                                        float &drho, float &ux, float &uy) {
+// force-corrected velocity u = (sum c h + F/2)/rho, drho = rho - 1.  SCALED: d in and out are
+// the offsets times `scale`, the power of two of the FP16 storage, so the stored words are
+// converted without a multiply (every rescaling by a power of two is exact).
+template <bool SCALED>
+__device__ __forceinline__ void collide_t(float d[9], float Fx, float Fy, float omega, float guo, float scale,
+                                          float inv_scale, float &drho, float &ux, float &uy) {
     float s0 = (d[0] + d[1]) + (d[2] + d[3]);
     float s1 = (d[4] + d[5]) + (d[6] + d[7]);
     drho = (s0 + s1) + d[8];
-    float jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]) + 0.5f * Fx;
-    float jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]) + 0.5f * Fy;
+    float jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+    float jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+    if (SCALED) {   // offsets held times the power-of-two storage scale: exact rescaling
+        drho *= inv_scale;
+        jx = fmaf(jx, inv_scale, 0.5f * Fx);
+        jy = fmaf(jy, inv_scale, 0.5f * Fy);
+    } else {
+        jx += 0.5f * Fx;
+        jy += 0.5f * Fy;
+    }
     float rho = 1.0f + drho;
     float ir = __builtin_amdgcn_rcpf(rho);   // 1 ulp; rho is within a few per cent of 1
     ux = jx * ir;
@@ -105,8 +125,13 @@ __device__ __forceinline__ void collide(float d[9], float Fx, float Fy, float om
         const float t = kCX[n] * ux + kCY[n] * uy;
         const float g = kCX[n] * Fx + kCY[n] * Fy;
         const float r = fmaf(t, fmaf(a2, t, a1), fmaf(g, fmaf(b2, t, b1), C0));
-        d[n] = fmaf(keep, d[n], kW[n] * r);
+        d[n] = fmaf(keep, d[n], (SCALED ? kW[n] * scale : kW[n]) * r);
     }
+}
+
+__device__ __forceinline__ void collide(float d[9], float Fx, float Fy, float omega, float guo,
+                                        float &drho, float &ux, float &uy) {
+    collide_t<false>(d, Fx, Fy, omega, guo, 1.0f, 1.0f, drho, ux, uy);
 }
 
 // ---- stiffness C~(P) (App. B) via piecewise cubics of a2/s and a4/s^2 in s = |P|^2 ---------

@@ -619,7 +619,7 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             rS[b1][2][tid] = pin.S2;
             float d[9];
 #pragma unroll
-            for (int q = 0; q < 9; ++q) d[q] = Pop<HT>::cvt(pin.H[q], is);
+            for (int q = 0; q < 9; ++q) d[q] = Pop<HT>::cvt_stored(pin.H[q]);   // times the storage scale
             // prefetch for iteration j+1: P(f+1), sigma(f), and the populations pulled into row
             // f-1: h_n(x, r) = h*_n(x - c_n, r - c_n) from rows f-2, f-1, f
             if (j + 1 < niter) {
@@ -691,14 +691,14 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                 else if (nib < 0)
                     ib_force(S, bodies, cur, (int)x, (int)rm2, Fx, Fy);
                 float drho, ux, uy;
-                collide(d, Fx, Fy, S.omega, S.guo, drho, ux, uy);
+                collide_t<Pop<HT>::kScaled>(d, Fx, Fy, S.omega, S.guo, sc, is, drho, ux, uy);
                 rV[o0][0][tid] = ux;
                 rV[o0][1][tid] = uy;
                 const int r = wi.y0 + j - 6;   // = f - 2
                 if (colE && r >= wi.y0 && r < wi.y0 + wi.l) {
                     const unsigned o = rm2 * nx + x;
 #pragma unroll
-                    for (int q = 0; q < 9; ++q) Pop<HT>::st(hout, (unsigned)q * N + o, d[q], sc);
+                    for (int q = 0; q < 9; ++q) Pop<HT>::st_stored(hout, (unsigned)q * N + o, d[q]);
                     if (nib > 0)
                         ib_store_v_list(sIB, nib, (int)nx, (int)ny, (int)x, (int)rm2, ux, uy);
                     else if (nib < 0)
