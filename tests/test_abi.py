@@ -54,7 +54,7 @@ def test_query_arena_bytes_scales_with_the_lattice():
     assert rc3 == lb.LB_OK and b3 < b1          # FP16 populations take less memory
 
 
-@pytest.mark.parametrize("bad", ["tau", "nx", "nodes", "P_clamp", "precision"])
+@pytest.mark.parametrize("bad", ["tau", "nx", "nx7", "ny7", "threads", "nodes", "P_clamp", "precision"])
 def test_validation_rejects_invalid_input(bad):
     spec = wl.small_case(3, 48, 40).sims[0]
     opt = None
@@ -62,6 +62,10 @@ def test_validation_rejects_invalid_input(bad):
         spec.params["tau"] = 0.5
     elif bad == "nx":
         spec.nx = 0
+    elif bad in ("nx7", "ny7"):   # below the 8 x 8 minimum
+        spec = wl.small_case(3, 7 if bad == "nx7" else 8, 7 if bad == "ny7" else 8, n_bodies=0).sims[0]
+    elif bad == "threads":
+        opt = lb.make_options(fused_threads=96)
     elif bad == "nodes":
         spec.bodies[0].R = np.zeros((2000, 2))
     elif bad == "P_clamp":

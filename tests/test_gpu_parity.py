@@ -163,3 +163,45 @@ def test_graph_replay_matches_eager():
         fa, fb = a.fields(), b.fields()
         for k in lb.FIELDS:
             assert np.array_equal(fa[k], fb[k]), k
+
+
+def test_launch_shapes_agree_bitwise():
+    """Every work-group size (one, two or four waves per block, so strips of 56, 120 or 248
+    columns) and segment length gives the same bits: a site's arithmetic does not depend on which
+    work item computes it.  One shape is also checked against the oracle."""
+    w = wl.small_case(45, 150, 90, n_bodies=2, radius=6.0, pull=2e-4)
+    shapes = [(64, 5), (128, 9), (256, 13), (64, 31), (128, 90)]
+    say(f"case launch shapes 150x90 seed=45 two bodies, 150 steps, (threads, rows) {shapes}")
+    out = []
+    for T, seg in shapes:
+        g = lb.Sim(w, lb.make_options(fused_threads=T, seg_rows=seg))
+        g.step(150)
+        out.append((g.fields(), g.nodes()))
+        say("  shape", g.launch_shape())
+        g.close()
+    for (f, n), (T, seg) in zip(out[1:], shapes[1:]):
+        for k in lb.FIELDS:
+            assert np.array_equal(f[k], out[0][0][k]), (T, seg, k)
+        for b in range(len(n)):
+            assert np.array_equal(n[b], out[0][1][b]), (T, seg, b)
+    r = oracle_sim(w.sims[0])
+    r.run(150)
+    g = lb.Sim(w, lb.make_options(fused_threads=64, seg_rows=5))
+    g.step(150)
+    compare(g, r)
+
+
+@pytest.mark.parametrize("nx,ny", [(8, 8), (8, 13), (11, 8)])
+def test_smallest_lattices(nx, ny):
+    """The smallest lattices the library accepts (8 x 8): narrower than one strip of any work-group
+    size and about as short as the 8-row pipeline fill, so columns and rows wrap inside one work
+    item; no bodies, random directors."""
+    w = wl.small_case(46, nx, ny, n_bodies=0)
+    say(f"case smallest lattice {nx}x{ny} seed=46 no bodies, 200 steps")
+    for T in (64, 128):
+        g = lb.Sim(w, lb.make_options(fused_threads=T))
+        r = oracle_sim(w.sims[0])
+        g.step(200)
+        r.run(200)
+        compare(g, r)
+        g.close()
