@@ -509,6 +509,7 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
     if (blockIdx.x == 0 && tid == 0) d_t[0] = d_t[0] + 1;   // the body update after this step uses t+1
 
     for (int vi = blockIdx.x; vi < n_items; vi += gridDim.x) {
+        __syncthreads();   // the previous item's last stages have read the item tables below
         const WorkItem wi = items[xcd_remap(vi, n_items)];
         const SimDev &S = sims[wi.sim];
         const unsigned nx = (unsigned)S.nx, ny = (unsigned)S.ny;
@@ -609,6 +610,15 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             const int b1 = (j + 59) % 3, b2 = (j + 58) % 3, b3 = (j + 57) % 3;           // stress rows f-1 .. f-3
             const int o1 = (j + 1) & 1, o0 = j & 1;   // rows f-1 / f-3 (odd lag) and f-2 / f-4 (even lag)
 
+            // One barrier per iteration.  Every value a stage reads from another lane was written
+            // in an earlier iteration (stage B reads P rows written by A one or more iterations
+            // ago, C the Ericksen row B wrote last iteration, D the velocity row C wrote last
+            // iteration, E the predictor row D wrote last iteration); what a stage reads from the
+            // current iteration is its own column, written by its own lane.  Every slot written
+            // here last held a row that an earlier iteration read.  So one barrier between
+            // consecutive iterations orders all of it.
+            __syncthreads();
+
             // ---- stage A: commit P(f), sigma(f-1); take this iteration's populations
             if (POL) {
                 rP[a0][0][tid] = pin.P0;
@@ -648,7 +658,6 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                     pout.H[8] = Pop<HT>::ld_raw(hin, bhi || xw ? 6u * N + own : 8u * N + yp + xm);
                 }
             }
-            __syncthreads();
 
             // ---- stage B: Ericksen stress at row f-1
             exy3 = exy2;
@@ -669,7 +678,6 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                 exy1 = E[1];
                 eyy1 = E[3];
             }
-            __syncthreads();
 
             // ---- stage C: force, moments, collision at row f-2
             if (j >= 4 && colC) {
@@ -705,7 +713,6 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                         ib_store_v(S, bodies, cur, (int)x, (int)rm2, ux, uy);
                 }
             }
-            __syncthreads();
 
             // ---- stage D: predictor at row f-3 (from j = 5 only the carried centre values)
             if (j >= 5 && colD) {
@@ -757,7 +764,6 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                 cout.p0 = Pc[0];
                 cout.p1 = Pc[1];
             }
-            __syncthreads();
 
             // ---- stage E: corrector at row f-4 with the inputs stage D froze one iteration ago;
             // from j = 7 it records the predicted centre values as next iteration's south row
