@@ -205,3 +205,31 @@ def test_smallest_lattices(nx, ny):
         r.run(200)
         compare(g, r)
         g.close()
+
+
+def test_watchdog_reports_a_blow_up():
+    """A body force far beyond the lattice's stable range makes the run blow up; the FP64 mass
+    watchdog reports it as LB_EUNSTABLE at a later call instead of returning garbage."""
+    w = wl.small_case(47, 48, 40, n_bodies=0, gx=0.05)
+    say("case watchdog 48x40 seed=47 gx=0.05, watchdog every 10 steps")
+    g = lb.Sim(w, lb.make_options(watchdog_every=10, graph_chunk=10))
+    with pytest.raises(lb.LBError) as e:
+        for _ in range(50):
+            g.step(20)
+            g.sync()
+    say("  raised:", e.value)
+    assert e.value.code == lb.LB_EUNSTABLE
+
+
+def test_patch_overflow_is_reported():
+    """A pull large enough to move nodes by several sites per step takes the body out of its force
+    patch; the body kernel flags it and the next call returns LB_ERANGE."""
+    w = wl.small_case(48, 96, 64, n_bodies=1, radius=5.0, pull=30.0)
+    say("case patch overflow 96x64 seed=48 pull=30")
+    g = lb.Sim(w, lb.make_options(graph_chunk=10))
+    with pytest.raises(lb.LBError) as e:
+        for _ in range(20):
+            g.step(10)
+            g.sync()
+    say("  raised:", e.value)
+    assert e.value.code == lb.LB_ERANGE
