@@ -265,7 +265,7 @@ def main():
         log(f"bench: copied {n * 4} bytes 5 times")
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no multi-GPU "
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): liblb has no multi-GPU "
               "path; independent simulations shard across GPUs with no exchange and one large lattice would "
               "use slab halos, neither of which is built.", file=sys.stderr)
         sys.exit(2)
