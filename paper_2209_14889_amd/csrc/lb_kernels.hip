@@ -243,6 +243,41 @@ __global__ __launch_bounds__(256) void k_ib_nodes(const SimDev *__restrict__ sim
     if (wall) atomicOr(d_status, kStatusWall);
 }
 
+// f_IB at tile site (lx, ly) = sum over the listed nodes, in list (node) order, of
+// f_a phi(x) phi(y), from each node's 4x4 footprint origin o (tile coordinates) and its
+// separable weights.  The LDS reads of four nodes are issued before any of them is used, so
+// each group of four costs one LDS round trip instead of two per node.
+__device__ __forceinline__ void gather_one(int lx, int ly, int2 o, float4 wxv, float4 wyv, double2 f, double &fx,
+                                           double &fy) {
+    const int i = lx - o.x, jj = ly - o.y;
+    if ((unsigned)i < 4u && (unsigned)jj < 4u) {
+        const float wxs = i == 0 ? wxv.x : i == 1 ? wxv.y : i == 2 ? wxv.z : wxv.w;
+        const float wys = jj == 0 ? wyv.x : jj == 1 ? wyv.y : jj == 2 ? wyv.z : wyv.w;
+        const double w = (double)wxs * (double)wys;
+        fx += f.x * w;
+        fy += f.y * w;
+    }
+}
+__device__ __forceinline__ void gather_site(const int2 *sI, const float4 (*sW)[2], const double2 *sF, int cnt, int lx,
+                                            int ly, double &fx, double &fy) {
+    int q = 0;
+    for (; q + 4 <= cnt; q += 4) {
+        int2 o[4];
+        float4 wx[4], wy[4];
+        double2 f[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            o[u] = sI[q + u];
+            wx[u] = sW[q + u][0];
+            wy[u] = sW[q + u][1];
+            f[u] = sF[q + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) gather_one(lx, ly, o[u], wx[u], wy[u], f[u], fx, fy);
+    }
+    for (; q < cnt; ++q) gather_one(lx, ly, sI[q], sW[q][0], sW[q][1], sF[q], fx, fy);
+}
+
 // One block per (body, 16x16 tile of its patch): f_IB(r) = sum_a f_a phi phi (App. A) as a gather
 // over the nodes whose 4x4 footprint reaches the tile, summed in node order (deterministic).
 __global__ __launch_bounds__(256) void k_ib_spread(const BodyDev *__restrict__ bodies, const int2 *__restrict__ blk,
@@ -299,18 +334,7 @@ __global__ __launch_bounds__(256) void k_ib_spread(const BodyDev *__restrict__ b
     const int px = tx * kPatchTile + lx, py = ty * kPatchTile + ly;
     if (px < B.ps && py < B.ps) {
         double fx = 0.0, fy = 0.0;
-        for (int q = 0; q < cnt; ++q) {
-            const int2 o = sI[q];
-            const int i = lx - o.x, jj = ly - o.y;
-            if ((unsigned)i < 4u && (unsigned)jj < 4u) {
-                const float4 wxv = sW[q][0], wyv = sW[q][1];
-                const float wxs = i == 0 ? wxv.x : i == 1 ? wxv.y : i == 2 ? wxv.z : wxv.w;
-                const float wys = jj == 0 ? wyv.x : jj == 1 ? wyv.y : jj == 2 ? wyv.z : wyv.w;
-                const double w = (double)wxs * (double)wys;
-                fx += sF[q].x * w;
-                fy += sF[q].y * w;
-            }
-        }
+        gather_site(sI, sW, sF, cnt, lx, ly, fx, fy);
         const unsigned i = (unsigned)(py * B.ps + px);
         B.fib[i] = (float)fx;
         B.fib[(unsigned)(B.ps * B.ps) + i] = (float)fy;
@@ -451,18 +475,7 @@ __global__ __launch_bounds__(256) void k_ib_step(const SimDev *__restrict__ sims
     const int px = tx * kPatchTile + lx, py = ty * kPatchTile + ly;
     if (px < B.ps && py < B.ps) {
         double fx = 0.0, fy = 0.0;
-        for (int q = 0; q < cnt; ++q) {
-            const int2 o = sI[q];
-            const int i = lx - o.x, jj = ly - o.y;
-            if ((unsigned)i < 4u && (unsigned)jj < 4u) {
-                const float4 wxv = sW[q][0], wyv = sW[q][1];
-                const float wxs = i == 0 ? wxv.x : i == 1 ? wxv.y : i == 2 ? wxv.z : wxv.w;
-                const float wys = jj == 0 ? wyv.x : jj == 1 ? wyv.y : jj == 2 ? wyv.z : wyv.w;
-                const double w = (double)wxs * (double)wys;
-                fx += sF[q].x * w;
-                fy += sF[q].y * w;
-            }
-        }
+        gather_site(sI, sW, sF, cnt, lx, ly, fx, fy);
         const unsigned i = (unsigned)(py * B.ps + px);
         B.fib[i] = (float)fx;
         B.fib[(unsigned)(B.ps * B.ps) + i] = (float)fy;
