@@ -156,7 +156,7 @@ int lb_body_force(lb_handle *h, int32_t sim, int32_t body, double out[8]);
  * smaller than 10 * total bodies): the 8 values of lb_body_force, then [8..9] the area-weighted
  * restoring force, the sum over sites of (area of the site's unit cell [x-1/2, x+1/2] x
  * [y-1/2, y+1/2] inside the node polygon) * div sigma^p, which unlike out[0..1] varies
- * continuously as the body moves (the same integral over the body, Sec. 4 and Fig. 6, with a
+ * continuously as the body moves (the same integral over the body, Sec. III and Fig. 6, with a
  * different quadrature).  Synchronous. */
 int lb_body_forces(lb_handle *h, double *host_out, size_t n_out);
 

@@ -3,7 +3,7 @@
  * evaluated by hand-written gfx950 kernels (BF16 matrix-core products with FP32 accumulation,
  * FP32 master weights, Adam).  It maps simulation parameters (stress diffusion, relaxation time,
  * body radius, director angle, polarization magnitude) to the series the lattice Boltzmann method
- * produces for them; the LB run stays the fallback and the judge of its error.
+ * produces for them; the LB run stays the fallback and the reference for its error.
  *
  * Network: widths w[0] -> w[1] -> ... -> w[L]; tanh after every layer but the last.  Parameters
  * are one FP32 array, layer by layer: W_l (w[l+1] x w[l], row major) then b_l (w[l+1]).

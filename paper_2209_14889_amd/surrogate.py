@@ -1,9 +1,9 @@
 """Learned surrogate of the body's restoring-force time series, with the lattice Boltzmann run as
-fallback and as judge of its error.
+fallback and as the reference for its error.
 
 Inputs (5): stress diffusion D_p, relaxation time, body radius, director angle to the pull, and
 polarization magnitude P_eq (alpha = -P_eq^2).  Output: the viscoelastic restoring force on the
-body along the pull (the integral of div sigma^p over the body, Sec. 4 and Fig. 6) sampled every
+body along the pull (the integral of div sigma^p over the body, Sec. III and Fig. 6) sampled every
 64 steps of a 4096-step pull-and-release run on a 128 x 128 lattice (64 samples).  The integral is
 taken with area weights (each site's div sigma^p times the area of its unit cell inside the node
 polygon): the plain sum over the sites inside jumps by whole sites as the outline moves across the
