@@ -178,7 +178,7 @@ def arena_bytes(sims: list, options: Options | None = None) -> int:
 class Sim:
     """One handle: a single simulation or a batched ensemble of independent ones."""
 
-    def __init__(self, sims, options: Options | None = None, device: str = "cuda:0"):
+    def __init__(self, sims, options: Options | None = None, device: str = "cuda:0", library_stream: bool = False):
         import torch
         if isinstance(sims, Workload):
             sims = sims.sims
@@ -195,13 +195,14 @@ class Sim:
         check(lib().lb_query_arena_bytes(m.params, len(self.specs), ctypes.byref(self.options), ctypes.byref(n)))
         self.arena = torch.empty(int(n.value), dtype=torch.uint8, device=self.device)
         # a stream of our own (default priority): graph capture is not allowed on the legacy
-        # default stream
-        self.stream = torch.cuda.Stream(device=self.device)
+        # default stream.  library_stream: pass NULL, so the library creates (and destroys) one.
+        self.stream = None if library_stream else torch.cuda.Stream(device=self.device)
         torch.cuda.current_stream(self.device).synchronize()
         h = ctypes.c_void_p()
         check(lib().lb_create(m.params, len(self.specs), ctypes.byref(self.options),
                               ctypes.c_void_p(self.arena.data_ptr()), ctypes.c_size_t(self.arena.numel()),
-                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+                              ctypes.c_void_p(None if library_stream else self.stream.cuda_stream),
+                              ctypes.byref(h)))
         self.h = h
 
     # -- stepping ------------------------------------------------------------------------------

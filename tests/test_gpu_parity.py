@@ -125,6 +125,28 @@ def test_fused_and_multipass_agree():
         assert linf_rel(fa[k], fb[k]) <= 2e-5, k
 
 
+def test_library_created_stream():
+    """hip_stream = NULL: the library creates its own stream and destroys it with the handle.
+    Stepping in graph chunks, the watchdog and the read-back then give the same bits as on a
+    caller's stream."""
+    w = wl.small_case(64, 64, 48, n_bodies=1, radius=5.0)
+    say("case library-created stream 64x48 seed=64 steps=120, graph chunks of 20, watchdog every 40")
+    opt = lb.make_options(graph_chunk=20, watchdog_every=40)
+    out = []
+    for own in (False, True):
+        g = lb.Sim(w, opt, library_stream=own)
+        g.step(120)
+        g.sync()
+        out.append((g.fields(), g.nodes(), g.t))
+        g.close()
+    (fa, na, ta), (fb, nb, tb) = out
+    assert ta == tb == 120
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+    for x, y in zip(na, nb):
+        assert np.array_equal(x, y)
+
+
 def test_run_to_run_bitwise_determinism():
     w = wl.small_case(44, 64, 48, n_bodies=1, radius=5.0)
     say("case determinism 64x48 seed=44 steps=120")
