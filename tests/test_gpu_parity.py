@@ -86,6 +86,32 @@ def test_parity_c1_1000_steps():
     assert np.max(np.abs(area_g - area_r)) <= 1e-4 * np.max(np.abs(area_r)) + 1e-12
 
 
+def _c2_parity(checkpoints):
+    w = wl.c2()
+    say(f"case c2 512x512 seed=1002 fused, parity at steps {checkpoints}")
+    g = lb.Sim(w, lb.make_options(kernel=0, graph_chunk=100))
+    r = oracle_sim(w.sims[0])
+    t = 0
+    for c in checkpoints:
+        g.step(c - t)
+        r.run(c - t)
+        t = c
+        say(f" t={r.t}")
+        compare(g, r)
+    g.close()
+
+
+def test_parity_c2_1000_steps():
+    """The 512 x 512 workload (one body R 16, directors near 30 degrees) against the oracle."""
+    _c2_parity((200, 1000))
+
+
+@pytest.mark.slow
+def test_parity_c2_5000_steps():
+    """The 512 x 512 workload over its full 5000 steps (minutes of oracle time)."""
+    _c2_parity((1000, 5000))
+
+
 def test_area_weighted_force_of_uniform_divergence():
     """At t = 0 with sigma_xx = a x and sigma_xy = b y near the bodies, div sigma = (a + b, 0) at every
     site they touch, so the area-weighted force is (a + b) times the polygon area exactly (the
