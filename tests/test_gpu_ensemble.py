@@ -53,6 +53,42 @@ def test_ensemble_member_matches_oracle():
         assert e <= 1e-4, k
 
 
+def test_full_ensemble_in_the_bench_configuration():
+    """The 256-member ensemble (sides 64 to 512 drawn independently, 14.7 M sites per step) at full
+    size, in the configuration the benchmark times: FP32, 256-thread items of 41 rows, graph
+    chunks of 100.  Eight sampled members equal their single runs bit for bit, and the three
+    smallest of them match the oracle."""
+    w = wl.c4()
+    sims = w.sims
+    say(f"case full ensemble c4: {len(sims)} sims, {sum(s.nx * s.ny for s in sims)} sites, 256 x 41 items, "
+        "graph chunks of 100, 100 steps")
+    ens = lb.Sim(sims, lb.make_options(fused_threads=256, seg_rows=41, graph_chunk=100))
+    shape = ens.launch_shape()
+    say("  launch shape", shape)
+    assert shape["threads"] == 256 and shape["seg_rows"] == 41
+    ens.step(100)
+    pick = sorted(int(i) for i in np.random.default_rng(78).choice(len(sims), 8, replace=False))
+    for i in pick:
+        s = sims[i]
+        say(f"  member {i}: {s.nx}x{s.ny}")
+        one = lb.Sim([s], lb.make_options())
+        one.step(100)
+        a, b = ens.fields(i), one.fields(0)
+        for k in lb.FIELDS:
+            assert np.array_equal(a[k], b[k]), (i, k)
+        assert np.array_equal(ens.nodes(i)[0], one.nodes(0)[0]), i
+        one.close()
+    for i in sorted(pick, key=lambda j: sims[j].nx * sims[j].ny)[:3]:
+        r = oracle_sim(sims[i])
+        r.run(100)
+        g, o = ens.fields(i), r.observe()
+        errs = {k: linf_rel(g[k], o[k]) for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py")}
+        say(f"  member {i} vs oracle: " + ", ".join(f"{k} {v:.1e}" for k, v in errs.items()))
+        for k, v in errs.items():
+            assert v <= 1e-4, (i, k, v)
+    ens.close()
+
+
 def test_body_update_paths_agree():
     """Many patch tiles (here about a thousand) take the two-launch body update (nodes once, then
     the spreading tiles); a single simulation takes the one-launch form in which every tile block
