@@ -65,7 +65,7 @@ typedef struct {
                                    (x0, y0, x1, y1, ...) replacing the polygon; may be NULL */
 } lb_body_desc;
 
-/* One simulation on a periodic nx x ny lattice. */
+/* One simulation on an nx x ny lattice, periodic or bounded by walls (see `walls`). */
 typedef struct {
     int32_t nx, ny;             /* 8 .. 16384 each, nx*ny <= 1e8 */
     double tau;                 /* BGK relaxation time (eqBGK), > 0.5 */
@@ -88,7 +88,10 @@ typedef struct {
     const lb_body_desc *bodies;
     const double *init_P;       /* host 2*nx*ny (Px plane, Py plane) or NULL (P = 0) */
     const double *init_sigma;   /* host 3*nx*ny (sxx, syy, sxy) or NULL (sigma = 0) */
-    const double *init_h;       /* host 9*nx*ny pre-collision populations or NULL (rest state) */
+    const double *init_h;       /* host 9*nx*ny pre-collision populations h_n (eqLB: after streaming,
+                                   before the next collision; plane n = direction n) or NULL (the
+                                   rest state); with init_sigma, init_P and explicit node positions
+                                   it restarts a saved state */
 } lb_sim_params;
 
 typedef struct {
@@ -119,11 +122,15 @@ int lb_query_arena_bytes(const lb_sim_params *sims, int32_t n_sims, const lb_opt
  * lb_query_arena_bytes bytes, 256-byte aligned.  hip_stream: the stream (hipStream_t) all work
  * is issued on; NULL makes the library create its own.  Validates: tau > 0.5, 8 D_p < 2,
  * 0 < P_clamp < 1, eta_p > 0, sizes, node counts, and that every body's force patch fits the
- * lattice.  Uploads the initial state and spreads the initial body forces; synchronous. */
+ * lattice (LB_EINVAL otherwise, also for an arena not 256-byte aligned; LB_ENOMEM if arena_bytes
+ * is smaller than lb_query_arena_bytes).  Uploads the initial state and spreads the initial body
+ * forces; synchronous. */
 int lb_create(const lb_sim_params *sims, int32_t n_sims, const lb_options *opt,
               void *device_arena, size_t arena_bytes, void *hip_stream, lb_handle **out);
 
-/* Advance every simulation by n_steps >= 0 coupled steps (asynchronous on the stream). */
+/* Advance every simulation by n_steps >= 0 coupled steps (asynchronous on the stream; LB_EINVAL
+ * for n_steps < 0).  A watchdog or patch report from earlier steps that has completed by the
+ * call is returned here (LB_EUNSTABLE, LB_ERANGE) before any new work is queued. */
 int lb_step(lb_handle *h, int32_t n_steps);
 
 /* Field selection bits for lb_read_fields, in output order. */
