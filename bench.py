@@ -330,6 +330,25 @@ def main():
         log(f"bench: paper experiment {experiment}")
         if failure is not None:
             mlups = sites * done / dt / 1e6
+    pcie = None
+    if not paper:
+        # context, not `value`: the same run with its host traffic, i.e. a handle created from the
+        # host arrays (upload, initial spreading) and every field of every simulation read back
+        t_r = time.perf_counter()
+        for i in range(len(w.sims)):
+            sim.fields(i)
+        t_read = time.perf_counter() - t_r
+        torch.cuda.synchronize()
+        t_c = time.perf_counter()
+        up = lb.Sim(w, lb.make_options(precision=precision, kernel=args.kernel, graph_chunk=args.graph_chunk,
+                                       seg_rows=shape["seg_rows"], fused_threads=shape["threads"]))
+        up.sync()
+        t_up = time.perf_counter() - t_c
+        up.close()
+        pcie = {"value": round(sites * args.steps / (dt + t_up + t_read) / 1e6, 2), "unit": "MLUPS",
+                "upload_s": round(t_up, 4), "readback_s": round(t_read, 4)}
+        log(f"bench: with the host traffic (create from host arrays {t_up:.3f} s, read back every field "
+            f"{t_read:.3f} s): {pcie['value']} MLUPS")
     sim.close()
 
     # roofline of the dominant kernel: HIP events around every field-kernel launch on the
@@ -394,6 +413,8 @@ def main():
         "cpu_baseline": cpu,
         "surrogate": sur,
     }
+    if pcie is not None:
+        line["pcie_inclusive"] = pcie
     if experiment is not None:
         line["experiment"] = experiment
     print(json.dumps(line), flush=True)
