@@ -466,6 +466,25 @@ struct lb_handle {
     int *h_status = nullptr;   // pinned
     hipEvent_t ev_wd = nullptr;
     bool wd_pending = false;
+
+    // releases everything the handle created (also when lb_create fails part way); the arena
+    // belongs to the caller
+    ~lb_handle() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        for (auto &pr : pending_field) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+        for (auto &pr : pending_ib) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+        for (auto e : ev_pool) (void)hipEventDestroy(e);
+        if (ev_wd) (void)hipEventDestroy(ev_wd);
+        if (h_status) (void)hipHostFree(h_status);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
 };
 
 namespace {
@@ -613,9 +632,17 @@ int choose_fused_config(lb_handle *h) {
     }
     int t_saved = 0;
     HIPCHK(hipMemcpy(&t_saved, h->d_t, sizeof(int), hipMemcpyDeviceToHost));
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
+    // the two timing events, released on every return
+    struct EventPair {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~EventPair() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    HIPCHK(hipEventCreate(&ev.a));
+    HIPCHK(hipEventCreate(&ev.b));
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     // warm the clocks with the first candidate, then time every candidate in two passes and
     // keep each one's best pass (clock ramps and neighbours on the device add noise)
     {
@@ -649,8 +676,6 @@ int choose_fused_config(lb_handle *h) {
         if (tbest[ci] < tbest[bi]) bi = ci;
     const Cand pick = cand[bi];
     const float best = tbest[bi];
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     HIPCHK(hipMemcpy(h->d_t, &t_saved, sizeof(int), hipMemcpyHostToDevice));
     h->tuned_ms = best;
     return upload_items(h, pick.T, pick.seg, pick.grid);
@@ -1169,21 +1194,7 @@ int lb_launch_shape(lb_handle *h, int32_t *threads, int32_t *seg_rows, int32_t *
 
 int lb_destroy(lb_handle *h) {
     if (!h) return fail(LB_EINVAL, "handle is NULL");
-    (void)hipStreamSynchronize(h->stream);
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
-    for (auto &pr : h->pending_field) {
-        (void)hipEventDestroy(pr.first);
-        (void)hipEventDestroy(pr.second);
-    }
-    for (auto &pr : h->pending_ib) {
-        (void)hipEventDestroy(pr.first);
-        (void)hipEventDestroy(pr.second);
-    }
-    for (auto e : h->ev_pool) (void)hipEventDestroy(e);
-    if (h->ev_wd) (void)hipEventDestroy(h->ev_wd);
-    if (h->h_status) (void)hipHostFree(h->h_status);
-    if (h->own_stream) (void)hipStreamDestroy(h->stream);
-    delete h;
+    delete h;   // waits for the stream, then releases what the handle created
     return LB_OK;
 }
 
