@@ -228,6 +228,12 @@ struct lb_mlp {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     long step = 0;
+    // waits for the stream and releases it if the library created it (also when lb_mlp_create
+    // fails part way); the arena belongs to the caller
+    ~lb_mlp() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
     float *P() { return reinterpret_cast<float *>(base + lo.oP); }
     float *G() { return reinterpret_cast<float *>(base + lo.oG); }
     float *M1() { return reinterpret_cast<float *>(base + lo.oM1); }
@@ -410,8 +416,6 @@ int lb_mlp_train_step(lb_mlp *m, const float *X, const float *Y, int32_t batch, 
 
 int lb_mlp_destroy(lb_mlp *m) {
     if (!m) return fail(LB_EINVAL, "NULL argument");
-    (void)hipStreamSynchronize(m->stream);
-    if (m->own_stream) (void)hipStreamDestroy(m->stream);
     delete m;
     return LB_OK;
 }
