@@ -104,6 +104,20 @@ __global__ __launch_bounds__(256) void k_gemm(const float *__restrict__ A, long 
 }
 
 // db[n] = sum over rows of dZ(m, n); one block per 64 columns, fixed summation order
+// zero n bytes (n a multiple of 4, 4-byte aligned): a kernel rather than a memset node, so a caller
+// may capture the calls that clear state into a graph
+__global__ __launch_bounds__(256) void k_zero(unsigned *__restrict__ p, size_t n_words) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n_words; i += (size_t)gridDim.x * 256) p[i] = 0u;
+}
+
+static hipError_t zero_async(void *p, size_t bytes, hipStream_t st) {
+    const size_t words = bytes / 4;
+    if (words == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<size_t>((words + 255) / 256, 4096);
+    k_zero<<<blocks, 256, 0, st>>>(static_cast<unsigned *>(p), words);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_colsum(const float *__restrict__ dZ, int M, int N, float *__restrict__ db) {
     __shared__ float part[4][64];
     const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
@@ -347,7 +361,7 @@ int lb_mlp_create(const lb_mlp_config *cfg, void *arena, size_t arena_bytes, voi
             HIPCHK(hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking));
             m->own_stream = true;
         }
-        HIPCHK(hipMemsetAsync(m->base, 0, m->lo.oAct, m->stream));
+        HIPCHK(zero_async(m->base, m->lo.oAct, m->stream));
         HIPCHK(hipStreamSynchronize(m->stream));
         *out = m.release();
         return LB_OK;
@@ -359,8 +373,8 @@ int lb_mlp_create(const lb_mlp_config *cfg, void *arena, size_t arena_bytes, voi
 int lb_mlp_set_params(lb_mlp *m, const float *host) {
     if (!m || !host) return fail(LB_EINVAL, "NULL argument");
     HIPCHK(hipMemcpyAsync(m->P(), host, 4 * m->lo.n_params, hipMemcpyHostToDevice, m->stream));
-    HIPCHK(hipMemsetAsync(m->M1(), 0, 4 * m->lo.n_params, m->stream));
-    HIPCHK(hipMemsetAsync(m->M2(), 0, 4 * m->lo.n_params, m->stream));
+    HIPCHK(zero_async(m->M1(), 4 * m->lo.n_params, m->stream));
+    HIPCHK(zero_async(m->M2(), 4 * m->lo.n_params, m->stream));
     HIPCHK(hipStreamSynchronize(m->stream));
     m->step = 0;
     return LB_OK;
