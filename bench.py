@@ -77,18 +77,30 @@ KERNEL_SOURCES = ["paper_2209_14889_amd/csrc/lb_kernels.hip", "paper_2209_14889_
                   "paper_2209_14889_amd/csrc/lb_common.h"]
 
 
+def kernel_code_digest() -> str:
+    """sha256 of the fused kernel's sources with comments and white space removed: only a change of
+    the code itself makes committed counters stale."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        t = open(os.path.join(ROOT, p)).read()
+        t = re.sub(r"/\*.*?\*/", " ", t, flags=re.S)
+        t = re.sub(r"//[^\n]*", " ", t)
+        h.update(" ".join(t.split()).encode())
+    return h.hexdigest()
+
+
 def counted_traffic(workload_name: str, shape: dict):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summary (copy-kernel calibrated), or None when that summary is for another workload or launch
     shape, or the kernel sources changed since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles",
                         f"k_fused_{workload_name}_t{shape['threads']}_s{shape['seg_rows']}_hbm_counters.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read() for p in KERNEL_SOURCES)).hexdigest()
-    if d.get("sources_sha256") != h or d.get("workload") != workload_name:
+    if d.get("code_sha256") != kernel_code_digest() or d.get("workload") != workload_name:
         return None
     if d["launch"]["threads"] != shape["threads"] or d["launch"]["seg_rows"] != shape["seg_rows"]:
         return None
@@ -121,7 +133,6 @@ def counters_summary(outdir: str, workload_name: str, threads: int, seg_rows: in
     WRITE_SIZE, in <outdir>/pmc_copy_f, pmc_copy_w, pmc_<workload>_f, pmc_<workload>_w) into the
     calibrated HBM traffic of one fused launch of the given shape:
     profiles/k_fused_<workload>_t<threads>_s<seg_rows>_hbm_counters.{json,md}."""
-    import hashlib
     copy_bytes = 64 * 1024 * 1024 * 4
     cf, _, _ = _counter_kib(os.path.join(outdir, "pmc_copy_f"), "__amd_rocclr_copyBuffer")
     cw, _, _ = _counter_kib(os.path.join(outdir, "pmc_copy_w"), "__amd_rocclr_copyBuffer")
@@ -138,9 +149,7 @@ def counters_summary(outdir: str, workload_name: str, threads: int, seg_rows: in
         "copy_bytes": copy_bytes, "fetch_scale": fetch_scale, "write_scale": write_scale,
         "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw, "dispatches": [nf, nw],
         "fetch_bytes": kf * 1024.0 * fetch_scale, "write_bytes": kw * 1024.0 * write_scale,
-        "algorithmic_bytes": alg, "sources": KERNEL_SOURCES,
-        "sources_sha256": hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read()
-                                                  for p in KERNEL_SOURCES)).hexdigest(),
+        "algorithmic_bytes": alg, "sources": KERNEL_SOURCES, "code_sha256": kernel_code_digest(),
     }
     d["traffic_bytes"] = d["fetch_bytes"] + d["write_bytes"]
     base = os.path.join(ROOT, "profiles", f"k_fused_{workload_name}_t{threads}_s{seg_rows}_hbm_counters")

@@ -1,6 +1,8 @@
 // HIP kernels of liblb for gfx950 (MI355X).
 //
-//   k_ib          immersed-body node update (App. A), node forces and force spreading
+//   k_ib_step     immersed-body update (App. A): node Heun step, node forces and force spreading
+//                 in one launch, for a step with few patch tiles
+//   k_ib_nodes, k_ib_spread   the same in two launches (nodes once per body, then the tiles)
 //   k_fused       one pass per step over every lattice site: forces, BGK + Guo collide with pull
 //                 streaming, velocity gradient, stiffness, Heun stress and polarization
 //   k_mp_*        the same step as four simple site-parallel kernels (debug / reference path)
@@ -10,8 +12,9 @@
 // The fused kernel walks a strip of columns down its rows like a pipeline.  Iteration j loads the
 // polarization of row f = y0 - 4 + j and the stress of row f-1, forms the Ericksen stress at row
 // f-1, collides row f-2, predicts row f-3 and corrects row f-4.  Every stage only needs rows that
-// earlier stages or earlier iterations produced, so each value is computed once per column and
-// row exchanges go through small LDS ring buffers.
+// earlier stages or earlier iterations produced, so within a work item each value is computed
+// once (the items overlap only by the pipeline's halo rows and columns) and row exchanges go
+// through small LDS ring buffers.
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
