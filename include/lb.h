@@ -109,7 +109,12 @@ typedef struct {
                                    the live state in lb_create and keep the fastest; 0: cost model */
     int32_t grid;               /* fused work-groups launched: 0 = one per work item; > 0 = a
                                    persistent grid of that many looping over the items */
-    int32_t reserved[2];
+    const char *autotune_cache; /* with autotune = 1: path of a text file of tuned launch shapes,
+                                   one line per key (the simulations' sizes and walls, P or not,
+                                   precision, field kernel, fused_threads and the GPU model); a key
+                                   found there is used without timing, a new one is tuned and its
+                                   shape appended.  NULL: no file.  A missing, unreadable or
+                                   garbled file only means tuning again */
 } lb_options;
 
 /* Bytes of device memory lb_create needs for these simulations (arena for all state, tables,

@@ -200,6 +200,7 @@ struct Plan {
 struct Opt {
     int precision = 0, shift = kDefaultShift, watchdog = 0, chunk = 0, kernel = 0, timing = 0, seg = 0, threads = 0;
     int autotune = 0, grid = 0;
+    std::string cache;   // autotune cache file, empty: none
 };
 
 Opt read_opt(const lb_options *o) {
@@ -215,6 +216,7 @@ Opt read_opt(const lb_options *o) {
     r.threads = o->fused_threads;
     r.autotune = o->autotune;
     r.grid = o->grid;
+    if (o->autotune_cache) r.cache = o->autotune_cache;
     return r;
 }
 
@@ -592,6 +594,70 @@ int upload_items(lb_handle *h, int T, int seg, int grid = 0) {
     return LB_OK;
 }
 
+// ---- autotune cache: one line per tuned key, "lbtune1 <key> <threads> <seg_rows> <grid> <ms>" ----
+
+// FNV-1a over everything the tuned shape depends on: the lattices (sizes, walls, P or not), the
+// storage precision, the field kernel, a forced work-group size, and the GPU (model, CUs)
+uint64_t tune_key(const lb_handle *h, const std::vector<lb_sim_params> &sims, int dev) {
+    uint64_t k = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            k ^= (v >> (8 * b)) & 0xffu;
+            k *= 1099511628211ull;
+        }
+    };
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        for (const char *c = prop.gcnArchName; *c; ++c) mix((uint64_t)(unsigned char)*c);
+        mix((uint64_t)prop.multiProcessorCount);
+    }
+    mix((uint64_t)h->opt.precision);
+    mix((uint64_t)h->opt.kernel);
+    mix((uint64_t)h->opt.threads);
+    mix((uint64_t)sims.size());
+    for (const auto &p : sims) {
+        mix((uint64_t)p.nx);
+        mix((uint64_t)p.ny);
+        mix((uint64_t)p.walls);
+        mix((uint64_t)(p.init_P != nullptr));
+    }
+    return k;
+}
+
+// the cached shape for `key`, if the file holds a well-formed line for it (the last one wins)
+bool tune_lookup(const std::string &path, uint64_t key, int &T, int &seg, int &grid, float &ms) {
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return false;
+    bool found = false;
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        unsigned long long k = 0;
+        int t = 0, sg = 0, gr = 0;
+        float m = 0.f;
+        if (std::sscanf(line, "lbtune1 %llx %d %d %d %f", &k, &t, &sg, &gr, &m) == 5 && k == key &&
+            (t == 64 || t == 128 || t == 256) && sg >= 1 && sg <= 4096 && gr >= 0) {
+            T = t;
+            seg = sg;
+            grid = gr;
+            ms = m;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+// append one line (a single short write, so concurrent writers do not interleave within it)
+void tune_store(const std::string &path, uint64_t key, int T, int seg, int grid, float ms) {
+    char line[128];
+    const int n = std::snprintf(line, sizeof line, "lbtune1 %016llx %d %d %d %.9g\n", (unsigned long long)key, T, seg,
+                                grid, (double)ms);
+    FILE *f = std::fopen(path.c_str(), "a");
+    if (!f) return;
+    if (n > 0) std::fwrite(line, 1, (size_t)n, f);
+    std::fclose(f);
+}
+
 // Work-group size and segment length of the fused kernel.  Default: the cost model with the
 // device's compute units and the kernel's occupancy.  With opt.autotune, every candidate pair
 // (T, seg) near the model's choices is timed with HIP events on the live state: a launch reads
@@ -613,6 +679,15 @@ int choose_fused_config(lb_handle *h) {
         int T = model_T();
         int seg = h->opt.seg ? h->opt.seg : model_seg(h->plan.sims, T, cus * fused_blocks_per_cu(T, fp16, h->any_walls, h->any_pol));
         return upload_items(h, T, seg, h->opt.grid);
+    }
+    const uint64_t key = tune_key(h, h->params, dev);
+    if (!h->opt.cache.empty()) {
+        int T = 0, seg = 0, grid = 0;
+        float ms = 0.f;
+        if (tune_lookup(h->opt.cache, key, T, seg, grid, ms)) {
+            h->tuned_ms = ms;
+            return upload_items(h, T, seg, grid);
+        }
     }
     struct Cand {
         int T, seg, grid;
@@ -678,6 +753,7 @@ int choose_fused_config(lb_handle *h) {
     const float best = tbest[bi];
     HIPCHK(hipMemcpy(h->d_t, &t_saved, sizeof(int), hipMemcpyHostToDevice));
     h->tuned_ms = best;
+    if (!h->opt.cache.empty()) tune_store(h->opt.cache, key, pick.T, pick.seg, pick.grid, best);
     return upload_items(h, pick.T, pick.seg, pick.grid);
 }
 

@@ -57,7 +57,7 @@ class Options(ctypes.Structure):
         ("watchdog_every", ctypes.c_int32), ("graph_chunk", ctypes.c_int32),
         ("kernel", ctypes.c_int32), ("timing", ctypes.c_int32), ("seg_rows", ctypes.c_int32),
         ("fused_threads", ctypes.c_int32), ("autotune", ctypes.c_int32), ("grid", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("autotune_cache", ctypes.c_char_p),
     ]
 
 
@@ -109,11 +109,12 @@ def check(rc: int) -> None:
 
 def make_options(precision: int = 0, fp16_shift: int = 0, watchdog_every: int = 0, graph_chunk: int = 0,
                  kernel: int = 0, timing: int = 0, seg_rows: int = 0, fused_threads: int = 0,
-                 autotune: int = 0, grid: int = 0) -> Options:
+                 autotune: int = 0, grid: int = 0, autotune_cache: str | None = None) -> Options:
     o = Options()
     o.precision, o.fp16_shift, o.watchdog_every, o.graph_chunk = precision, fp16_shift, watchdog_every, graph_chunk
     o.kernel, o.timing, o.seg_rows, o.fused_threads = kernel, timing, seg_rows, fused_threads
     o.autotune, o.grid = autotune, grid
+    o.autotune_cache = None if autotune_cache is None else os.fsencode(autotune_cache)
     return o
 
 

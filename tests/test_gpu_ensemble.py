@@ -89,6 +89,42 @@ def test_full_ensemble_in_the_bench_configuration():
     ens.close()
 
 
+def test_autotune_cache(tmp_path):
+    """lb_options.autotune_cache: the first tuned create appends its shape under the workload's key;
+    a second create of the same workload takes the shape from the file without timing (the same
+    shape and stored milliseconds, no new line); another workload adds its own line; a garbled
+    file only means tuning again."""
+    cache = str(tmp_path / "tune.txt")
+    opt = lb.make_options(autotune=1, autotune_cache=cache)
+    w = wl.small_case(65, 96, 80, n_bodies=1)
+    say("case autotune cache 96x80 and 64x48 seed=65")
+
+    def shape(work):
+        g = lb.Sim(work, opt)
+        s = g.launch_shape()
+        g.step(4)
+        g.sync()
+        g.close()
+        return s
+
+    def lines():
+        with open(cache) as f:
+            return f.read().splitlines()
+
+    a = shape(w)
+    assert len(lines()) == 1 and lines()[0].startswith("lbtune1 ") and a["tuned_ms"] > 0
+    b = shape(w)
+    assert b == a, (a, b)
+    assert len(lines()) == 1
+    shape(wl.small_case(65, 64, 48, n_bodies=1))
+    assert len(lines()) == 2
+    with open(cache, "w") as f:
+        f.write("garbage\nlbtune1 zz 1 2\n")
+    c = shape(w)
+    assert (c["threads"] in (64, 128, 256)) and c["tuned_ms"] > 0
+    assert len(lines()) == 3
+
+
 def test_body_update_paths_agree():
     """Many patch tiles (here about a thousand) take the two-launch body update (nodes once, then
     the spreading tiles); a single simulation takes the one-launch form in which every tile block
