@@ -126,8 +126,9 @@ int lb_query_arena_bytes(const lb_sim_params *sims, int32_t n_sims, const lb_opt
  * batched ensemble; sizes may differ).  device_arena: caller-owned device memory of at least
  * lb_query_arena_bytes bytes, 256-byte aligned.  hip_stream: the stream (hipStream_t) all work
  * is issued on; NULL makes the library create its own.  Validates: tau > 0.5, 8 D_p < 2,
- * 0 < P_clamp < 1, eta_p > 0, sizes, node counts, and that every body's force patch fits the
- * lattice (LB_EINVAL otherwise, also for an arena not 256-byte aligned; LB_ENOMEM if arena_bytes
+ * 0 < P_clamp < 1, eta_p > 0, sizes, node counts, that every body's force patch fits the
+ * lattice and that no two bodies' bounding circles (centre of the nodes, farthest node)
+ * intersect, across periodic directions too (LB_EINVAL otherwise, also for an arena not 256-byte aligned; LB_ENOMEM if arena_bytes
  * is smaller than lb_query_arena_bytes).  Uploads the initial state and spreads the initial body
  * forces; synchronous. */
 int lb_create(const lb_sim_params *sims, int32_t n_sims, const lb_options *opt,

@@ -220,6 +220,20 @@ Opt read_opt(const lb_options *o) {
     return r;
 }
 
+// centre of a body: the mean of its nodes, or the polygon's centre
+void body_centre(const lb_body_desc &b, double &cx, double &cy) {
+    cx = b.cx;
+    cy = b.cy;
+    if (!b.nodes) return;
+    cx = cy = 0.0;
+    for (int a = 0; a < b.n_nodes; ++a) {
+        cx += b.nodes[2 * a];
+        cy += b.nodes[2 * a + 1];
+    }
+    cx /= b.n_nodes;
+    cy /= b.n_nodes;
+}
+
 double body_extent(const lb_body_desc &b) {
     if (!b.nodes) return b.radius;
     double cx = 0, cy = 0;
@@ -264,11 +278,9 @@ int validate(const lb_sim_params *sims, int n_sims, const Opt &o) {
             if (d.trap_k != 0.0 && (!(d.trap_w > 0.0) || !(d.trap_t2 >= d.trap_t1) || !std::isfinite(d.trap_k)))
                 return fail(LB_EINVAL, "sim %d body %d: trap needs trap_w > 0 and trap_t2 >= trap_t1", s, b);
             double ext = body_extent(d);
-            int ps = 2 * (int)std::ceil(ext) + 24;
             int lim = std::min(p.nx, p.ny);
             if (2 * (int)std::ceil(ext) + 8 > lim)
                 return fail(LB_EINVAL, "sim %d body %d: body too large for the lattice", s, b);
-            (void)ps;
             if (p.walls) {
                 // every node's kernel footprint (rows floor(y) - 1 .. floor(y) + 2) inside the walls,
                 // with one row to spare for the predicted position
@@ -293,6 +305,25 @@ int validate(const lb_sim_params *sims, int n_sims, const Opt &o) {
                     return fail(LB_EINVAL, "sim %d body %d: a node's kernel footprint reaches a wall", s, b);
             }
         }
+        // bodies do not overlap: their bounding circles (centre of the nodes, farthest node) stay
+        // apart, measured across the periodic directions
+        for (int b = 0; b < p.n_bodies; ++b)
+            for (int c = b + 1; c < p.n_bodies; ++c) {
+                double xb, yb, xc, yc;
+                body_centre(p.bodies[b], xb, yb);
+                body_centre(p.bodies[c], xc, yc);
+                double dx = std::fabs(xb - xc), dy = std::fabs(yb - yc);
+                if (p.walls != 2) {
+                    dx = std::fmod(dx, (double)p.nx);
+                    dx = std::min(dx, p.nx - dx);
+                }
+                if (p.walls == 0) {
+                    dy = std::fmod(dy, (double)p.ny);
+                    dy = std::min(dy, p.ny - dy);
+                }
+                if (std::hypot(dx, dy) < body_extent(p.bodies[b]) + body_extent(p.bodies[c]))
+                    return fail(LB_EINVAL, "sim %d: bodies %d and %d overlap", s, b, c);
+            }
     }
     return LB_OK;
 }

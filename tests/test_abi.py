@@ -87,6 +87,21 @@ def test_mlp_sizes_are_host_side():
     assert mlp.lib().lb_mlp_query_bytes(ctypes.byref(bad), ctypes.byref(n)) != lb.LB_OK
 
 
+def test_validation_rejects_overlapping_bodies():
+    spec = wl.small_case(3, 96, 64, n_bodies=2, radius=5.0).sims[0]
+    assert _query([spec])[0] == lb.LB_OK
+    b0, b1 = spec.bodies
+    b1.R = b1.R - b1.R.mean(axis=0) + b0.R.mean(axis=0) + np.array([8.0, 0.0])   # centres 8 apart, R 5
+    rc, _ = _query([spec])
+    assert rc != lb.LB_OK and "overlap" in lb.lib().lb_last_error().decode()
+    # across the periodic boundary too: centres at x = 2 and x = 92 on a 96-wide lattice
+    b0.R = b0.R - b0.R.mean(axis=0) + np.array([2.0, 32.0])
+    b1.R = b1.R - b1.R.mean(axis=0) + np.array([92.0, 32.0])
+    assert _query([spec])[0] != lb.LB_OK
+    b1.R = b1.R + np.array([-20.0, 0.0])   # 26 apart across the boundary: no overlap
+    assert _query([spec])[0] == lb.LB_OK
+
+
 def test_validation_rejects_bodies_at_walls():
     spec = wl.small_case(3, 48, 40, walls=1).sims[0]
     rc, _ = _query([spec])
