@@ -54,11 +54,20 @@ def test_query_arena_bytes_scales_with_the_lattice():
     assert rc3 == lb.LB_OK and b3 < b1          # FP16 populations take less memory
 
 
-@pytest.mark.parametrize("bad", ["tau", "nx", "nx7", "ny7", "threads", "nodes", "P_clamp", "precision"])
+@pytest.mark.parametrize("bad", ["nsims0", "tau", "nx", "nx7", "ny7", "threads", "nodes", "P_clamp", "precision",
+                                 "eta_p", "D_p"])
 def test_validation_rejects_invalid_input(bad):
     spec = wl.small_case(3, 48, 40).sims[0]
     opt = None
-    if bad == "tau":
+    if bad == "nsims0":   # an empty list of simulations
+        rc, _ = _query([], opt)
+        assert rc != lb.LB_OK and lb.lib().lb_last_error().decode()
+        return
+    if bad == "eta_p":
+        spec.params["eta_p"] = 0.0
+    elif bad == "D_p":
+        spec.params["D_p"] = 0.25   # 8 D_p = 2: the explicit diffusion step is no longer stable
+    elif bad == "tau":
         spec.params["tau"] = 0.5
     elif bad == "nx":
         spec.nx = 0

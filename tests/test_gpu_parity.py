@@ -255,6 +255,26 @@ def test_smallest_lattices(nx, ny):
         g.close()
 
 
+def test_degenerate_parameters_and_zero_steps():
+    """Limits of the model that lb_create accepts: eta_p = +inf (no polymer relaxation, a purely
+    elastic stress) with D_p = 0 (no stress diffusion); and lb_step(0), which changes nothing."""
+    w = wl.small_case(66, 56, 44, n_bodies=1, radius=5.0, D_p=0.0, eta_p=math.inf)
+    say("case degenerate parameters 56x44 seed=66 eta_p=inf D_p=0, 200 steps")
+    g = lb.Sim(w, lb.make_options())
+    f0 = g.fields()
+    g.step(0)
+    g.sync()
+    assert g.t == 0
+    f1 = g.fields()
+    for k in lb.FIELDS:
+        assert np.array_equal(f0[k], f1[k]), k
+    r = oracle_sim(w.sims[0])
+    g.step(200)
+    r.run(200)
+    compare(g, r)
+    g.close()
+
+
 def test_watchdog_reports_a_blow_up():
     """A body force far beyond the lattice's stable range makes the run blow up; the FP64 mass
     watchdog reports it as LB_EUNSTABLE at a later call instead of returning garbage."""
