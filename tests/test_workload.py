@@ -110,6 +110,28 @@ def test_return_closed_forms():
     assert experiment.return_value((0.0, 0.0), (-50.0, 0.0), 100.0) == 0.5       # overshoot back
 
 
+def test_wall_speeds_split_the_box_into_wall_band_and_bulk():
+    """The wall-mode diagnostic of the sweeps: the largest speed within `band` sites of any wall,
+    and elsewhere.  A stand-in for the simulation supplies the two velocity planes."""
+    class Fields:
+        def __init__(self, vx, vy):
+            self.vx, self.vy = vx, vy
+
+        def fields(self, names=None):
+            return {"vx": self.vx, "vy": self.vy}
+
+    ny, nx = 20, 30
+    vx, vy = np.zeros((ny, nx)), np.zeros((ny, nx))
+    vx[1, 15] = 3.0          # inside the band at the south wall
+    vy[10, 28] = 4.0         # inside the band at the east wall
+    vx[10, 15], vy[10, 15] = 0.6, 0.8   # bulk, |v| = 1
+    vx[2, 2] = 2.0           # just outside a two-site band: bulk
+    wall, bulk = experiment.wall_speeds(Fields(vx, vy), band=2)
+    assert wall == 4.0 and bulk == 2.0
+    wall, bulk = experiment.wall_speeds(Fields(vx, vy), band=3)   # (2, 2) joins the band
+    assert wall == 4.0 and bulk == 1.0
+
+
 def test_bench_refuses_several_gpus():
     bench = os.path.join(os.path.dirname(HERE), "bench.py")
     r = subprocess.run([sys.executable, bench, "--gpus", "2"], capture_output=True, text=True, timeout=300)
