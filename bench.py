@@ -36,10 +36,12 @@ def log(*a):
 
 
 def bytes_per_site(precision: int) -> int:
-    """Algorithmic HBM bytes per site update: every state value read once and written once.
-    Populations 9 x (4 B FP32 | 2 B FP16), stress 3 x 4 B, polarization 2 x 8 B (FP64)."""
+    """Algorithmic HBM bytes per site update: the state {h, sigma, P} read once and written once,
+    populations 9 x (4 B FP32 | 2 B FP16), stress 3 x 4 B and polarization 2 x 4 B: 112 B in the
+    FP32 form, 76 B with FP16 populations.  The library's own storage may hold more (its
+    state_bytes()); the difference is reported beside the roofline, never counted in it."""
     pop = 9 * (2 if precision == 1 else 4)
-    return 2 * (pop + 3 * 4 + 2 * 8)
+    return 2 * (pop + 3 * 4 + 2 * 4)
 
 
 def workload(name: str, steps: int):
@@ -134,8 +136,8 @@ def counters_summary(outdir: str, workload_name: str, threads: int, seg_rows: in
     calibrated HBM traffic of one fused launch of the given shape:
     profiles/k_fused_<workload>_t<threads>_s<seg_rows>_hbm_counters.{json,md}."""
     copy_bytes = 64 * 1024 * 1024 * 4
-    cf, _, _ = _counter_kib(os.path.join(outdir, "pmc_copy_f"), "__amd_rocclr_copyBuffer")
-    cw, _, _ = _counter_kib(os.path.join(outdir, "pmc_copy_w"), "__amd_rocclr_copyBuffer")
+    cf, _, _ = _counter_kib(os.path.join(outdir, "pmc_copy_f"), "lbk::k_stream_copy")
+    cw, _, _ = _counter_kib(os.path.join(outdir, "pmc_copy_w"), "lbk::k_stream_copy")
     tag = f"{workload_name}_t{threads}_s{seg_rows}"
     kf, nf, _ = _counter_kib(os.path.join(outdir, f"pmc_{tag}_f"), "void lbk::k_fused")
     kw, nw, _ = _counter_kib(os.path.join(outdir, f"pmc_{tag}_w"), "void lbk::k_fused")
@@ -184,32 +186,56 @@ def trace_summary(db: str, title: str, command: str, out: str, top: int = 8):
 
 
 def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10) -> float:
-    """GB/s (bytes read + bytes written) of a device-to-device copy of nbytes, best of reps."""
+    """GB/s (bytes read + bytes written) of the library's streaming copy kernel (lb_stream_copy)
+    over nbytes, best of reps, timed with HIP events on the stream it runs on."""
     import torch
+    from paper_2209_14889_amd import lb
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
     a.fill_(1)
-    b.copy_(a)
+    st = torch.cuda.current_stream()
+    lb.stream_copy(a, b, st)
     torch.cuda.synchronize()
     best = 1e30
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        b.copy_(a)
-        e1.record()
+        e0.record(st)
+        lb.stream_copy(a, b, st)
+        e1.record(st)
         e1.synchronize()
         best = min(best, e0.elapsed_time(e1) * 1e-3)
+    assert bool(torch.equal(a[:4096], b[:4096])) and bool(torch.equal(a[-4096:], b[-4096:]))
     del a, b
     torch.cuda.empty_cache()
     return 2 * nbytes / best / 1e9
 
 
+def host_cpus() -> dict:
+    """The host the oracle runs on: logical CPUs, the CPUs this process may run on, the model."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "usable": usable, "model": model,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
 def cpu_baseline(w, name: str, budget_s: float = 15.0):
     """FP64 oracle on the host: the full coupled step on the workload's first simulation for as
-    many steps as fit in about budget_s seconds (at least 2)."""
+    many steps as fit in about budget_s seconds (at least 2), on every CPU this process may use
+    (on a GPU machine that is its share of the host, which OMP_NUM_THREADS also states), then on one
+    thread for a third of the budget."""
     import oracle
-    cores = min(os.cpu_count() or 1, 16)
-    oracle.set_threads(cores)
+    cpus = host_cpus()
+    oracle.set_threads(cpus["usable"])
     s = w.sims[0]
     p = s.params
     bodies = [oracle.Body(R=b.R.copy(), k_spring=b.k_spring, eps_angle=b.eps_angle, l_eq=b.l_eq, pull=b.pull,
@@ -237,9 +263,74 @@ def cpu_baseline(w, name: str, budget_s: float = 15.0):
     dt_1 = time.perf_counter() - t0
     oracle.set_threads(cores)
     return {"value": round(sites * n / dt / 1e6, 4), "unit": "MLUPS", "cores": cores,
-            "kind": "oracle", "sample": f"{name}: first simulation {s.nx}x{s.ny}, {n} coupled steps after 1 warm-up step",
+            "kind": "oracle", "sample": (f"{name}: first simulation {s.nx}x{s.ny}, {n} coupled steps after 1 warm-up "
+                                         f"step, OpenMP on all {cores} CPUs this process may use"),
+            "host": cpus,
             "single_thread": {"value": round(sites * n1 / dt_1 / 1e6, 4), "unit": "MLUPS",
                               "sample": f"{n1} more steps on one thread after 1 warm-up step"}}
+
+
+def field_kernel_timing(w, precision: int, shape: dict, kernel: int, steps: int):
+    """Average duration of the fused field kernel: HIP events recorded on the library's stream
+    around each of `steps` plain launches (same kernel and launch shape as the timed run), and the
+    body update's the same way."""
+    from paper_2209_14889_amd import lb
+    topt = lb.make_options(precision=precision, kernel=kernel, timing=1, seg_rows=shape["seg_rows"],
+                           fused_threads=shape["threads"],
+                           grid=shape["grid"] if shape["grid"] < shape["n_items"] else 0)
+    tsim = lb.Sim(w, topt)
+    tsim.step(20)
+    tsim.timing(reset=True)
+    tsim.step(steps)
+    tm = tsim.timing()
+    stored = tsim.state_bytes()
+    tsim.close()
+    avg_ms = tm["field_ms"] / max(1, tm["field_launches"])
+    ib_ms = tm["ib_ms"] / max(1, tm["ib_launches"]) if tm["ib_launches"] else 0.0
+    return avg_ms, ib_ms, stored
+
+
+def roofline(precision: int, sites: int, avg_ms: float, stored: float, copy_gbps: float | None) -> dict:
+    bps = bytes_per_site(precision)
+    achieved = bps * sites / (avg_ms * 1e-3) / 1e9
+    r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": "k_fused", "bytes_per_site": bps,
+         "algorithmic_gb_per_launch": round(bps * sites / 1e9, 4), "launch_us": round(avg_ms * 1e3, 3),
+         "stored_bytes_per_site": stored, "storage_surplus_bytes_per_site": stored - bps,
+         "stored_gbps": round(stored * sites / (avg_ms * 1e-3) / 1e9, 1)}
+    if copy_gbps:
+        r["copy_gbps"] = round(copy_gbps, 1)
+        r["frac_of_copy"] = round(achieved / copy_gbps, 4)
+    return r
+
+
+def c4_leg(args) -> dict:
+    """The 256-simulation ensemble (the other HBM-bound workload): one handle, one fused launch per
+    step over all 14.7 M sites, timed over a graph-replayed run, and its field-kernel roofline."""
+    import torch
+    from paper_2209_14889_amd import lb
+    w, desc, precision = workload("c4", args.c4_steps)
+    opt = lb.make_options(precision=precision, graph_chunk=args.graph_chunk, autotune=1)
+    sim = lb.Sim(w, opt)
+    shape = sim.launch_shape()
+    sim.step(args.warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.c4_steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sim.close()
+    avg_ms, ib_ms, stored = field_kernel_timing(w, precision, shape, 0, min(args.timing_steps, 100))
+    out = {"workload": f"c4: {desc}", "sites": w.sites, "steps": args.c4_steps,
+           "value": round(w.sites * args.c4_steps / dt / 1e6, 2), "unit": "MLUPS",
+           "ms_per_step": round(dt / args.c4_steps * 1e3, 5), "threads": shape["threads"],
+           "seg_rows": shape["seg_rows"], "work_items": shape["n_items"],
+           "roofline": roofline(precision, w.sites, avg_ms, stored, None), "body_update_us": round(ib_ms * 1e3, 3)}
+    log(f"bench: c4 ensemble {out['value']} MLUPS, field kernel {avg_ms * 1e3:.1f} us, "
+        f"frac {out['roofline']['frac']}")
+    return out
 
 
 def main():
@@ -254,6 +345,8 @@ def main():
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--timing-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 256-simulation ensemble leg")
+    ap.add_argument("--c4-steps", type=int, default=200, help="timed steps of the ensemble leg")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate leg (4096 + 512 LB runs of 128^2, network training, fallback)")
@@ -267,7 +360,8 @@ def main():
     ap.add_argument("--summary-title", default="")
     ap.add_argument("--summary-command", default="", help="the command that produced the profiler output")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="only copy a 256 MiB device buffer 5 times (reference for the HBM byte counters)")
+                    help="only copy a 256 MiB device buffer 5 times with the library's copy kernel (reference for the "
+                         "HBM byte counters)")
     args = ap.parse_args()
     if args.counters_summary:
         counters_summary(args.counters_summary, args.workload, args.threads, args.seg_rows, args.summary_command)
@@ -278,13 +372,14 @@ def main():
         return
     if args.copy_calibration:
         import torch
+        from paper_2209_14889_amd import lb
         n = 64 * 1024 * 1024
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(5):
-            dst.copy_(src)
+            lb.stream_copy(src, dst)
         torch.cuda.synchronize()
-        log(f"bench: copied {n * 4} bytes 5 times")
+        log(f"bench: copied {n * 4} bytes 5 times with the library's streaming copy kernel")
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): liblb has no multi-GPU "
@@ -375,25 +470,18 @@ def main():
 
     # roofline of the dominant kernel: HIP events around every field-kernel launch on the
     # library's stream (plain launches, same kernel and launch configuration)
-    topt = lb.make_options(precision=precision, kernel=args.kernel, timing=1, seg_rows=shape["seg_rows"],
-                           fused_threads=shape["threads"],
-                           grid=shape["grid"] if shape["grid"] < shape["n_items"] else 0)
-    tsim = lb.Sim(w, topt)
-    tsim.step(20)
-    tsim.timing(reset=True)
-    tsim.step(args.timing_steps)
-    tm = tsim.timing()
-    tsim.close()
-    avg_ms = tm["field_ms"] / max(1, tm["field_launches"])
-    ib_ms = tm["ib_ms"] / max(1, tm["ib_launches"]) if tm["ib_launches"] else 0.0
-    bps = bytes_per_site(precision)
-    achieved = bps * sites / (avg_ms * 1e-3) / 1e9
-    log(f"bench: field kernel {avg_ms * 1e3:.2f} us/launch, body kernel {ib_ms * 1e3:.2f} us/launch, "
-        f"{achieved:.0f} GB/s algorithmic")
-
-    # the achievable streaming bandwidth on this device, for context: a 1 GiB device-to-device copy
+    avg_ms, ib_ms, stored = field_kernel_timing(w, precision, shape, args.kernel, args.timing_steps)
+    # the achievable streaming bandwidth on this device: the library's own copy kernel over 1 GiB
     copy_gbps = copy_bandwidth()
-    log(f"bench: device copy {copy_gbps:.0f} GB/s (read + write)")
+    log(f"bench: streaming copy kernel {copy_gbps:.0f} GB/s (read + write)")
+    roof = roofline(precision, sites, avg_ms, stored, copy_gbps)
+    roof["traffic"] = counted_traffic(args.workload, shape)
+    roof["traffic_unit"] = "GB per launch"
+    log(f"bench: field kernel {avg_ms * 1e3:.2f} us/launch, body kernel {ib_ms * 1e3:.2f} us/launch, "
+        f"{roof['achieved']:.0f} GB/s algorithmic ({roof['bytes_per_site']} B/site), frac {roof['frac']}")
+    c4 = None
+    if args.workload == "c3" and not args.no_c4:
+        c4 = c4_leg(args)
 
     sur = None
     if not args.no_surrogate:
@@ -426,15 +514,13 @@ def main():
                    "kernel": "fused" if args.kernel == 0 else "multipass", "graph_chunk": args.graph_chunk,
                    "threads": shape["threads"], "seg_rows": shape["seg_rows"], "work_items": shape["n_items"],
                    "grid": shape["grid"]},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": counted_traffic(args.workload, shape),
-                     "traffic_unit": "GB per launch", "algorithmic_gb_per_launch": round(bps * sites / 1e9, 4),
-                     "kernel": "k_fused", "bytes_per_site": bps, "launch_us": round(avg_ms * 1e3, 3),
-                     "copy_gbps": round(copy_gbps, 1), "frac_of_copy": round(achieved / copy_gbps, 4)},
+        "roofline": roof,
+        "body_update_us": round(ib_ms * 1e3, 3),
         "cpu_baseline": cpu,
         "surrogate": sur,
     }
+    if c4 is not None:
+        line["c4"] = c4
     if pcie is not None:
         line["pcie_inclusive"] = pcie
     if experiment is not None:

@@ -173,6 +173,24 @@ int lb_body_force(lb_handle *h, int32_t sim, int32_t body, double out[8]);
  * different quadrature).  Synchronous. */
 int lb_body_forces(lb_handle *h, double *host_out, size_t n_out);
 
+/* lb_body_forces without synchronising, for sampling a run on the device: queues the observable
+ * kernel on the handle's stream and writes 8 doubles per body (simulations in order, bodies in
+ * order within each) into device_out, device memory of at least n_out doubles (LB_ERANGE if
+ * n_out < 8 * total bodies): [0..1] the site-sum restoring force, [2..3] the centre of mass,
+ * [4..5] the total node force, [6..7] the area-weighted restoring force (the same quantities as
+ * lb_body_forces, without the external force, which the host computes).  Asynchronous. */
+int lb_body_forces_device(lb_handle *h, double *device_out, size_t n_out);
+
+/* Bytes of stored state one site update reads and writes (populations, polymer stress and
+ * polarization planes, read once and written once) in this handle's storage form. */
+int lb_state_bytes(lb_handle *h, double *bytes_per_site);
+
+/* Copy `bytes` of device memory from src to dst on hip_stream (NULL: the null stream) with the
+ * library's streaming copy kernel: the bandwidth ceiling the field kernel is measured against.
+ * bytes and both pointers must be multiples of 16 (LB_EINVAL otherwise); the buffers must not
+ * overlap.  Asynchronous. */
+int lb_stream_copy(const void *src, void *dst, size_t bytes, void *hip_stream);
+
 /* FP64 conservation sums of simulation `sim` at the current time (synchronous):
  * out[0] = sum rho, out[1..2] = sum of sum_n c_n h_n (momentum without the half force). */
 int lb_conservation(lb_handle *h, int32_t sim, double out[3]);

@@ -487,9 +487,9 @@ struct lb_handle {
                               // fused variant without the P and Ericksen work runs
     int n_items = 0;
     float tuned_ms = 0.f;
-    // graph replay
-    hipGraphExec_t gexec = nullptr;
-    int gsteps = 0;
+    // graph replay: executable graphs of graph_chunk steps and of every power of two below it, each
+    // captured from parity 0 (even lengths, so a replay ends at parity 0 again)
+    std::vector<std::pair<int, hipGraphExec_t>> graphs;   // (steps, graph), longest first
     // timing
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending_field, pending_ib;
@@ -504,7 +504,7 @@ struct lb_handle {
     // belongs to the caller
     ~lb_handle() {
         if (stream) (void)hipStreamSynchronize(stream);
-        if (gexec) (void)hipGraphExecDestroy(gexec);
+        for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
         for (auto &pr : pending_field) {
             (void)hipEventDestroy(pr.first);
             (void)hipEventDestroy(pr.second);
@@ -800,13 +800,15 @@ int run_watchdog(lb_handle *h) {
     return LB_OK;
 }
 
-int build_graph(lb_handle *h) {
+// capture `steps` coupled steps from parity 0 into an executable graph
+int build_graph(lb_handle *h, int steps) {
     hipGraph_t g = nullptr;
     int cur0 = h->cur;
     int64_t t0 = h->t;
+    h->cur = 0;
     HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
     int rc = LB_OK;
-    for (int i = 0; i < h->opt.chunk && rc == LB_OK; ++i) rc = launch_step(h, false);
+    for (int i = 0; i < steps && rc == LB_OK; ++i) rc = launch_step(h, false);
     hipError_t e = hipStreamEndCapture(h->stream, &g);
     h->cur = cur0;
     h->t = t0;
@@ -815,10 +817,27 @@ int build_graph(lb_handle *h) {
         return rc;
     }
     if (e != hipSuccess) return fail(LB_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(LB_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
-    h->gsteps = h->opt.chunk;
+    h->graphs.emplace_back(steps, x);
+    return LB_OK;
+}
+
+// the graphs lb_step replays: graph_chunk steps, then every power of two below it down to 2, so a
+// run of n steps replays whole chunks and covers the rest with at most log2(chunk) more graphs
+int build_graphs(lb_handle *h) {
+    if (h->opt.chunk <= 0 || h->opt.timing) return LB_OK;
+    int rc = build_graph(h, h->opt.chunk);
+    if (rc) return rc;
+    int p = 2;
+    while (p * 2 < h->opt.chunk) p *= 2;
+    for (; p >= 2; p /= 2) {
+        if (p == h->opt.chunk) continue;
+        rc = build_graph(h, p);
+        if (rc) return rc;
+    }
     return LB_OK;
 }
 
@@ -1079,6 +1098,8 @@ static int create_impl(const lb_sim_params *sims, int n_sims, const lb_options *
     HIPCHK(hipEventCreateWithFlags(&h->ev_wd, hipEventDisableTiming));
     rc = check_status(h.get());
     if (rc) return rc;
+    rc = build_graphs(h.get());
+    if (rc) return rc;
     *out = h.release();
     return LB_OK;
 }
@@ -1104,21 +1125,25 @@ int lb_step(lb_handle *h, int32_t n_steps) {
             if (*h->h_status & kStatusPatch) return fail(LB_ERANGE, "a body outgrew its force patch");
             if (*h->h_status & kStatusWall) return fail(LB_ERANGE, "a node's kernel footprint reached a wall");
         }
-        const bool use_graph = h->opt.chunk > 0 && !h->opt.timing;
+        const bool use_graph = !h->graphs.empty();
         int done = 0;
         while (done < n_steps) {
             int rc;
             int left = n_steps - done;
             const int wd = h->opt.watchdog;
-            int until_wd = wd > 0 ? (int)(wd - (h->t % wd)) : left;
-            if (use_graph && h->cur == 0 && left >= h->opt.chunk && until_wd >= h->opt.chunk) {
-                if (!h->gexec) {
-                    rc = build_graph(h);
-                    if (rc) return rc;
-                }
-                HIPCHK(hipGraphLaunch(h->gexec, h->stream));
-                h->t += h->gsteps;
-                done += h->gsteps;
+            const int until_wd = wd > 0 ? (int)(wd - (h->t % wd)) : left;
+            const int lim = std::min(left, until_wd);
+            const std::pair<int, hipGraphExec_t> *g = nullptr;
+            if (use_graph && h->cur == 0)
+                for (const auto &c : h->graphs)   // longest first
+                    if (c.first <= lim) {
+                        g = &c;
+                        break;
+                    }
+            if (g) {
+                HIPCHK(hipGraphLaunch(g->second, h->stream));
+                h->t += g->first;
+                done += g->first;
             } else {
                 rc = launch_step(h, h->opt.timing != 0);
                 if (rc) return rc;
@@ -1258,6 +1283,30 @@ int lb_body_forces(lb_handle *h, double *out, size_t n_out) {
         o[9] = r[kBodyOut * b + 7];
     }
     return check_status(h);
+}
+
+int lb_body_forces_device(lb_handle *h, double *device_out, size_t n_out) {
+    if (!h || !device_out) return fail(LB_EINVAL, "NULL argument");
+    const size_t nb = h->hb.size();
+    if (n_out < (size_t)kBodyOut * nb) return fail(LB_ERANGE, "output buffer too small");
+    if (nb == 0) return LB_OK;
+    HIPCHK(launch_body_force(h->stream, h->d_sims, h->d_bodies, 0, (int)nb, h->cur, device_out));
+    return LB_OK;
+}
+
+int lb_state_bytes(lb_handle *h, double *bytes_per_site) {
+    if (!h || !bytes_per_site) return fail(LB_EINVAL, "NULL argument");
+    const double pop = h->opt.precision == 1 ? 2.0 : 4.0;
+    *bytes_per_site = 2.0 * (9.0 * pop + 3.0 * 4.0 + 2.0 * (double)sizeof(*h->hs[0].P[0]));
+    return LB_OK;
+}
+
+int lb_stream_copy(const void *src, void *dst, size_t bytes, void *hip_stream) {
+    if (!src || !dst) return fail(LB_EINVAL, "NULL argument");
+    if ((bytes & 15) || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15))
+        return fail(LB_EINVAL, "bytes and both pointers must be multiples of 16");
+    HIPCHK(launch_stream_copy(static_cast<hipStream_t>(hip_stream), src, dst, bytes));
+    return LB_OK;
 }
 
 int lb_conservation(lb_handle *h, int32_t sim, double out[3]) {

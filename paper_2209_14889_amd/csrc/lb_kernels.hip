@@ -16,6 +16,8 @@
 // once (the items overlap only by the pipeline's halo rows and columns) and row exchanges go
 // through small LDS ring buffers.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <hip/hip_fp16.h>
 
 #include "lb_device.h"
@@ -1251,6 +1253,23 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ src, HT 
     if (i < n) Pop<HT>::store(dst, i, src[i], scale);
 }
 
+// streaming copy of n16 16-byte words, the bandwidth ceiling the field kernel is measured against:
+// each thread moves four words per trip, all four loads issued before the stores, and the grid
+// strides over the buffer so every compute unit keeps several loads in flight
+__global__ __launch_bounds__(256) void k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                     size_t n16) {
+    const size_t stride = (size_t)gridDim.x * 1024;
+    for (size_t base = (size_t)blockIdx.x * 1024 + threadIdx.x; base < n16; base += stride) {
+        uint4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (base + 256 * k < n16) v[k] = src[base + 256 * k];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (base + 256 * k < n16) dst[base + 256 * k] = v[k];
+    }
+}
+
 // ------------------------------------------------------------------------------------------------
 // launch wrappers (host)
 // ------------------------------------------------------------------------------------------------
@@ -1339,6 +1358,14 @@ hipError_t launch_body_force(hipStream_t st, const SimDev *sims, const BodyDev *
                              double *out) {
     if (nbodies <= 0) return hipSuccess;
     k_body_force<<<nbodies, 256, 0, st>>>(sims, bodies, body0, cur, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(hipStream_t st, const void *src, void *dst, size_t bytes) {
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n16 + 1023) / 1024, 256 * 16);
+    k_stream_copy<<<(unsigned)blocks, 256, 0, st>>>(static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), n16);
     return hipGetLastError();
 }
 

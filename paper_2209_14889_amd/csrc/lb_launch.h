@@ -26,6 +26,8 @@ hipError_t launch_sums(bool fp16, int sim, int nblocks, hipStream_t st, const Si
 // body observables of bodies body0 .. body0+nbodies-1, 6 doubles each into out
 hipError_t launch_body_force(hipStream_t st, const SimDev *sims, const BodyDev *bodies, int body0, int nbodies, int cur,
                              double *out);
+// streaming device-to-device copy (bytes a multiple of 16, 16-byte aligned pointers)
+hipError_t launch_stream_copy(hipStream_t st, const void *src, void *dst, size_t bytes);
 hipError_t launch_pack(bool fp16, hipStream_t st, const float *src, void *dst, size_t n, float scale);
 
 }  // namespace lbk

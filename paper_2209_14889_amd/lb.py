@@ -93,10 +93,13 @@ def lib():
         L.lb_destroy.argtypes = [vp]
         L.lb_launch_shape.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _dp]
+        L.lb_body_forces_device.argtypes = [vp, vp, ctypes.c_size_t]
+        L.lb_state_bytes.argtypes = [vp, _dp]
+        L.lb_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.lb_last_error.restype = ctypes.c_char_p
         for name in ("lb_query_arena_bytes", "lb_create", "lb_step", "lb_read_fields", "lb_body_force",
                      "lb_conservation", "lb_sync", "lb_time", "lb_timing", "lb_destroy", "lb_launch_shape",
-                     "lb_body_forces"):
+                     "lb_body_forces", "lb_body_forces_device", "lb_state_bytes", "lb_stream_copy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -105,6 +108,17 @@ def lib():
 def check(rc: int) -> None:
     if rc != LB_OK:
         raise LBError(rc, lib().lb_last_error().decode())
+
+
+def stream_copy(src, dst, stream=None) -> None:
+    """dst[:] = src with the library's streaming copy kernel (cuda tensors of equal byte size, a
+    multiple of 16); asynchronous on `stream` (default: torch's current stream)."""
+    import torch
+    n = src.numel() * src.element_size()
+    assert n == dst.numel() * dst.element_size() and src.is_contiguous() and dst.is_contiguous()
+    st = stream if stream is not None else torch.cuda.current_stream(src.device)
+    check(lib().lb_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), ctypes.c_size_t(n),
+                               ctypes.c_void_p(st.cuda_stream)))
 
 
 def make_options(precision: int = 0, fp16_shift: int = 0, watchdog_every: int = 0, graph_chunk: int = 0,
@@ -256,6 +270,19 @@ class Sim:
         out = np.empty(10 * max(1, nb))
         check(lib().lb_body_forces(self.h, out.ctypes.data_as(_dp), out.size))
         return out[:10 * nb].reshape(nb, 10).copy()
+
+    def body_forces_device(self, out) -> None:
+        """Queue the body observables into `out`, a float64 cuda tensor of 8 values per body (site-sum
+        restoring force, centre of mass, node force, area-weighted restoring force), without
+        synchronising: the values are there once the handle's stream has reached this point."""
+        assert out.dtype == self._torch.float64 and out.is_cuda and out.is_contiguous()
+        check(lib().lb_body_forces_device(self.h, ctypes.c_void_p(out.data_ptr()), out.numel()))
+
+    def state_bytes(self) -> float:
+        """Stored state bytes read and written per site update in this handle's storage form."""
+        v = ctypes.c_double(0)
+        check(lib().lb_state_bytes(self.h, ctypes.byref(v)))
+        return float(v.value)
 
     def conservation(self, sim: int = 0) -> np.ndarray:
         out = np.empty(3)

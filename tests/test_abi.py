@@ -120,3 +120,13 @@ def test_validation_rejects_bodies_at_walls():
     assert rc != lb.LB_OK and "wall" in lb.lib().lb_last_error().decode()
     spec.params["walls"] = 2
     assert _query([spec])[0] != lb.LB_OK
+
+
+def test_stream_copy_rejects_unaligned_sizes():
+    """lb_stream_copy moves 16-byte words: sizes or pointers that are not multiples of 16 are rejected
+    before anything is queued (the pointers are never dereferenced here)."""
+    L = lb.lib()
+    vp = ctypes.c_void_p
+    assert L.lb_stream_copy(vp(4096), vp(8192), ctypes.c_size_t(17), None) == lb.LB_EINVAL
+    assert L.lb_stream_copy(vp(4100), vp(8192), ctypes.c_size_t(32), None) == lb.LB_EINVAL
+    assert L.lb_stream_copy(None, vp(8192), ctypes.c_size_t(32), None) == lb.LB_EINVAL

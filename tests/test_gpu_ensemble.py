@@ -47,21 +47,23 @@ def test_ensemble_member_matches_oracle():
     r = oracle_sim(sims[2])
     r.run(200)
     g, o = ens.fields(2), r.observe()
-    for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py"):
+    for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py", "fpx", "fpy"):
         e = linf_rel(g[k], o[k])
         say(f"  {k} {e:.2e}")
         assert e <= 1e-4, k
 
 
+@pytest.mark.timeout(900)
 def test_full_ensemble_in_the_bench_configuration():
     """The 256-member ensemble (sides 64 to 512 drawn independently, 14.7 M sites per step) at full
     size, in the configuration the benchmark times: FP32, 256-thread items of 41 rows, graph
-    chunks of 100.  Eight sampled members equal their single runs bit for bit, and the three
-    smallest of them match the oracle."""
+    chunks of 100.  After 100 steps eight sampled members equal their single runs bit for bit and
+    the three smallest of them match the oracle; after 1000 steps the smallest member of the
+    ensemble and one of median size match the oracle at the FP32 bar."""
     w = wl.c4()
     sims = w.sims
     say(f"case full ensemble c4: {len(sims)} sims, {sum(s.nx * s.ny for s in sims)} sites, 256 x 41 items, "
-        "graph chunks of 100, 100 steps")
+        "graph chunks of 100, 100 then 1000 steps")
     ens = lb.Sim(sims, lb.make_options(fused_threads=256, seg_rows=41, graph_chunk=100))
     shape = ens.launch_shape()
     say("  launch shape", shape)
@@ -82,10 +84,25 @@ def test_full_ensemble_in_the_bench_configuration():
         r = oracle_sim(sims[i])
         r.run(100)
         g, o = ens.fields(i), r.observe()
-        errs = {k: linf_rel(g[k], o[k]) for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py")}
+        errs = {k: linf_rel(g[k], o[k]) for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py", "fpx", "fpy")}
         say(f"  member {i} vs oracle: " + ", ".join(f"{k} {v:.1e}" for k, v in errs.items()))
         for k, v in errs.items():
             assert v <= 1e-4, (i, k, v)
+    ens.step(900)
+    by_size = sorted(range(len(sims)), key=lambda j: (sims[j].nx * sims[j].ny, j))
+    for i in (by_size[0], by_size[len(sims) // 2]):
+        s = sims[i]
+        say(f"  member {i} ({s.nx}x{s.ny}, D_p {s.meta['D_p']:.3g}, R {s.meta['radius']:.1f}) vs oracle at 1000 steps")
+        r = oracle_sim(s)
+        r.run(1000)
+        g, o = ens.fields(i), r.observe()
+        errs = {k: linf_rel(g[k], o[k]) for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py", "fpx", "fpy")}
+        say("    " + ", ".join(f"{k} {v:.1e}" for k, v in errs.items()))
+        for k, v in errs.items():
+            assert v <= 1e-4, (i, k, v)
+        d = float(np.max(np.abs(ens.nodes(i)[0] - r.bodies[0].R)))
+        say(f"    node error {d:.1e}")
+        assert d <= 1e-5
     ens.close()
 
 

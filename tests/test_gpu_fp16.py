@@ -1,7 +1,9 @@
 """Precision form: populations stored as FP16 offsets from the rest weights (scaled by 2^S) with FP32
-arithmetic, against the FP64 oracle.  Bar: L-infinity-normalised relative error <= 1e-3 on velocity
-and stress after 1000 steps, on a 256 x 256 periodic window shaped like the 2048 x 2048 workload
-(near-uniform directors, two bodies of radius 12 and 16)."""
+arithmetic, against the FP64 oracle on the 2048 x 2048 workload's 256 x 256 crop: the periodic
+window of its initial state centred on body 0 (the only body in it), run by both as its own
+simulation.  Bar: L-infinity-normalised relative error <= 1e-3 on velocity, stress, polarization
+and the restoring-force density after 1000 steps; the errors at 5000 and at the workload's full
+20 000 steps are printed and reported."""
 import math
 import sys
 
@@ -19,36 +21,60 @@ def say(*a):
     sys.stdout.flush()
 
 
-def crop_case():
-    rng = np.random.default_rng(1003)
-    n = 256
-    th = math.radians(30.0) + rng.normal(0.0, 0.1, size=(n, n))
-    bodies = [wl.make_body(80.0, 96.0, 12.0, 75, (5e-5 * math.cos(0.7), 5e-5 * math.sin(0.7))),
-              wl.make_body(176.0, 160.0, 16.0, 101, (5e-5 * math.cos(2.9), 5e-5 * math.sin(2.9)))]
-    sim = wl.SimSpec(n, n, wl.base_params(200.0, 0.02), wl.director_field(th, math.sqrt(0.9)), bodies)
-    return wl.Workload("c3-crop", [sim], 1000, "fp16")
+FIELDS = ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py", "fpx", "fpy")
 
 
-def test_fp16_storage_within_1e3_of_oracle():
+def crop_case(side: int = 256) -> wl.Workload:
+    """The side x side periodic window of the 2048 x 2048 workload's initial state centred on body 0,
+    with that body moved into window coordinates; no node of another body lies in the window."""
+    full = wl.c3().sims[0]
+    b = full.bodies[0]
+    c = b.R.mean(axis=0)
+    x0, y0 = int(math.floor(c[0])) - side // 2, int(math.floor(c[1])) - side // 2
+    for other in full.bodies[1:]:
+        d = np.mod(other.R - np.array([x0, y0], dtype=np.float64), full.nx)
+        assert not np.any((d[:, 0] < side) & (d[:, 1] < side))
+    ys = np.arange(y0, y0 + side) % full.ny
+    xs = np.arange(x0, x0 + side) % full.nx
+    P = full.P0[:, ys][:, :, xs].copy()
+    R = b.R - np.array([x0, y0], dtype=np.float64)
+    assert R.min() > 8 and R.max() < side - 8
+    body = wl.BodySpec(R=R, k_spring=b.k_spring, eps_angle=b.eps_angle, l_eq=b.l_eq, pull=b.pull)
+    sim = wl.SimSpec(side, side, dict(full.params), P, [body], meta=dict(origin=(x0, y0)))
+    return wl.Workload("c3-crop", [sim], 20000, "fp16")
+
+
+def _errors(g, r):
+    a, o = g.fields(), r.observe()
+    errs = {k: linf_rel(a[k], o[k]) for k in FIELDS}
+    errs["rho-1"] = linf_rel(a["rho"] - 1.0, o["rho"] - 1.0)
+    errs["nodes"] = float(np.max(np.abs(g.nodes()[0] - r.bodies[0].R)))
+    return errs
+
+
+@pytest.mark.timeout(900)
+def test_fp16_storage_on_the_2048_workload_crop():
     w = crop_case()
-    say("case fp16 precision form 256x256 two bodies, 1000 steps")
+    say(f"case fp16 precision form: 256x256 crop of the 2048^2 workload at {w.sims[0].meta['origin']}, body 0 "
+        "(150 nodes, R 23.9), graph chunks of 100; checks at 1000, 5000, 20000 steps")
     g = lb.Sim(w, lb.make_options(precision=1, graph_chunk=100))
     r = oracle_sim(w.sims[0])
-    g.step(1000)
-    r.run(1000)
-    a, o = g.fields(), r.observe()
-    worst = 0.0
-    for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py"):
-        e = linf_rel(a[k], o[k])
-        worst = max(worst, e)
-        say(f"  {k} {e:.2e}")
-    for k in ("vx", "vy", "sxx", "syy", "sxy"):
-        assert linf_rel(a[k], o[k]) <= 1e-3, k
-    nodes = g.nodes()
-    for b in range(2):
-        d = float(np.max(np.abs(nodes[b] - r.bodies[b].R)))
-        say(f"  body {b} node error {d:.2e}")
-        assert d <= 1e-4
+    t = 0
+    for c in (1000, 5000, 20000):
+        g.step(c - t)
+        r.run(c - t)
+        t = c
+        errs = _errors(g, r)
+        say(f"  t={t}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+        if t == 1000:
+            for k in FIELDS:
+                assert errs[k] <= 1e-3, (t, k, errs[k])
+            assert errs["nodes"] <= 1e-4
+        else:
+            # reported; the bar of the stored form is the 1000-step one, this only catches drift
+            for k in FIELDS:
+                assert errs[k] <= 1e-2, (t, k, errs[k])
+    g.close()
 
 
 def test_fp16_shift_changes_nothing_structural():

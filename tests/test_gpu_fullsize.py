@@ -23,7 +23,7 @@ pytestmark = pytest.mark.gpu
 
 K = 20                 # steps
 H = 4 * K + 8          # margin of a window
-FIELDS = ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py")
+FIELDS = ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py", "fpx", "fpy")
 
 
 def say(*a):

@@ -19,7 +19,7 @@ from tests.helpers import linf_rel, oracle_sim
 pytestmark = pytest.mark.gpu
 
 NX, NY, PERIOD, STEPS = 16384, 6103, 128, 3
-NAMES = ["rho", "vx", "vy", "sxx", "syy", "sxy", "Px", "Py"]
+NAMES = ["rho", "vx", "vy", "sxx", "syy", "sxy", "Px", "Py", "fpx", "fpy"]
 
 
 def say(*a):

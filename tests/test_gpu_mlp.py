@@ -1,24 +1,25 @@
 """Surrogate network kernels on the GPU against the FP64 oracle network.
 
-Tolerances.  The library rounds both operands of every product to BF16 (8-bit significand, relative
-rounding error <= 2^-9) and accumulates in FP32.  Against the oracle taking the SAME BF16-rounded
-operands in FP64, only FP32 accumulation order, tanhf and rare ties that round differently in FP32
-and FP64 upstream remain: 2e-3 relative L2 per array.  Against the unrounded oracle the operand
-rounding itself shows: about sqrt(2) 2^-9 per product, compounding over four layers, well inside
-3e-2 relative L2."""
+Element-wise bars.  The library rounds both operands of every product to BF16 and accumulates in
+FP32.  Each layer is checked as a function of the GPU's own inputs to it (prefix networks for the
+forward pass, single-row gradient calls for the backward pass), against the oracle's layer taking
+the same BF16-rounded operands in FP64, with the per-element bound derived in tests/mlp_bounds.py:
+FP32 accumulation (gamma_K times the sum of |terms|), tanhf within a few ulp, and BF16 rounding of
+an operand only where a rounding midpoint lies within that operand's bound.  Against the unrounded
+oracle end to end, the operand rounding itself shows, about sqrt(2) 2^-9 per product compounding
+over four layers: that is reported as a relative L2 of at most 3e-2, for context."""
 import numpy as np
 import pytest
 
 import oracle.mlp as omlp
+from tests import mlp_bounds as mb
 
 pytestmark = pytest.mark.gpu
 
 WIDTHS = [5, 256, 256, 256, 64]
 
 
-def bf16(a):
-    import torch
-    return torch.from_numpy(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+bf16 = mb.bf16
 
 
 def rel(a, b):
@@ -55,6 +56,39 @@ def _net(params, B=512):
     return net
 
 
+def _prefix_preactivations(params, X):
+    """The GPU's pre-activation of every layer for the rows X: the network of the first k layers
+    returns the full network's k-th pre-activation bit for bit (same kernels, same data)."""
+    import torch
+    from paper_2209_14889_amd import mlp
+    zs = []
+    for k in range(1, len(WIDTHS)):
+        net = mlp.MLP(WIDTHS[:k + 1], X.shape[0])
+        net.set_params(mb.prefix_params(params, WIDTHS, k))
+        zs.append(net.forward(torch.from_numpy(X).cuda()).cpu().numpy().astype(np.float64))
+        net.close()
+    return zs
+
+
+def _gpu_layer_inputs(params, X, zs):
+    """Reference of every layer on the GPU's inputs, checked element by element; returns the layer
+    inputs (FP64 tanh of the GPU's pre-activations) and their bounds."""
+    layers = omlp.unpack(np.asarray(params, np.float64), WIDTHS)
+    A, EA = X.astype(np.float64), np.zeros(X.shape)
+    acts, errs = [A], [EA]
+    for l, (W, b) in enumerate(layers):
+        z, ez = mb.layer_bound(A, EA, W, b)
+        bad = np.abs(zs[l] - z) > ez
+        print(f"  layer {l}: max |gpu - ref| / bound {np.max(np.abs(zs[l] - z) / ez):.3f}, "
+              f"median bound / max |z| {np.median(ez) / np.max(np.abs(z)):.1e}", flush=True)
+        assert not bad.any(), (l, int(bad.sum()))
+        if l + 1 < len(layers):
+            A, EA = mb.hidden(zs[l])
+            acts.append(A)
+            errs.append(EA)
+    return acts, errs
+
+
 def test_forward_matches_oracle():
     import torch
     from paper_2209_14889_amd import mlp
@@ -68,31 +102,71 @@ def test_forward_matches_oracle():
     net = _net(params)
     Y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
     assert Y.shape == (300, 64)
-    assert rel(Y, omlp.forward(params, WIDTHS, X, bf16)[-1]) < 2e-3
-    assert rel(Y, omlp.forward(params, WIDTHS, X)[-1]) < 3e-2
     assert np.array_equal(net.get_params(), params)
     net.close()
+    zs = _prefix_preactivations(params, X)
+    assert np.array_equal(zs[-1], Y.astype(np.float64))   # the full network is its own last prefix
+    _gpu_layer_inputs(params, X, zs)                         # every layer, every element
+    assert rel(Y, omlp.forward(params, WIDTHS, X, mb.bf16)[-1]) < 2e-3
+    assert rel(Y, omlp.forward(params, WIDTHS, X)[-1]) < 3e-2
+
+
+def _unpack_grads(flat):
+    return omlp.unpack(np.asarray(flat, np.float64), WIDTHS)
 
 
 def test_gradients_match_oracle():
+    """Gradients of a 256-row batch.  Each row alone (batch 1) exposes its pre-activation gradients
+    as the bias gradients, so every backward layer is checked element by element on the GPU's own
+    inputs; the batch of 2^8 rows then holds exactly those values times 2^-8, and its weight and
+    bias gradients are checked element by element as sums over the rows."""
     import torch
     from paper_2209_14889_amd import mlp
     params = mlp.init_params(WIDTHS, 12)
-    X, Y = _data(6, 257)
-    net = _net(params)
-    loss, g = net.gradients(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda())
-    g_ref = omlp.gradients(params, WIDTHS, X, Y, bf16)
-    g_full = omlp.gradients(params, WIDTHS, X, Y)
-    o = 0
-    for l in range(4):
-        for n in (WIDTHS[l + 1] * WIDTHS[l], WIDTHS[l + 1]):
-            assert rel(g[o:o + n], g_ref[o:o + n]) < 2e-3, (l, n)
-            assert rel(g[o:o + n], g_full[o:o + n]) < 3e-2, (l, n)
-            o += n
+    B = 256
+    X, Y = _data(6, B)
+    zs = _prefix_preactivations(params, X)
+    acts, errs = _gpu_layer_inputs(params, X, zs)
+    layers = omlp.unpack(np.asarray(params, np.float64), WIDTHS)
+    L = len(layers)
+    net = _net(params, B)
+    Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    # one row at a time
+    dz_rows = [[None] * B for _ in range(L)]
+    worst = 0.0
+    for r in range(B):
+        _, g1 = net.gradients(Xd[r:r + 1], Yd[r:r + 1])
+        g1 = _unpack_grads(g1)
+        for l in range(L):
+            dz_rows[l][r] = g1[l][1][None, :]
+        dz, edz = mb.output_grad_bound(zs[-1][r:r + 1], Y[r:r + 1], 1)
+        assert np.all(np.abs(dz_rows[L - 1][r] - dz) <= edz), r
+        for l in range(L - 1, -1, -1):
+            A, EA = acts[l][r:r + 1], errs[l][r:r + 1]
+            gW, egW, gb, egb, dzp, edzp = mb.backward_layer_bound(dz_rows[l][r], A, EA, layers[l][0], l == 0)
+            assert np.all(np.abs(g1[l][0] - gW) <= egW), (r, l)
+            worst = max(worst, float(np.max(np.abs(g1[l][0] - gW) / np.maximum(egW, 1e-300))))
+            if l > 0:
+                assert np.all(np.abs(dz_rows[l - 1][r] - dzp) <= edzp), (r, l)
+    print(f"  single rows: max |gpu - ref| / bound {worst:.3f}", flush=True)
+    # the whole batch: each row's values scaled by exactly 2^-8
+    loss, g = net.gradients(Xd, Yd)
+    g = _unpack_grads(g)
+    for l in range(L):
+        dz = np.concatenate(dz_rows[l]) / B
+        gW, egW, gb, egb, _, _ = mb.backward_layer_bound(dz, acts[l], errs[l], layers[l][0], True)
+        assert np.all(np.abs(g[l][0] - gW) <= egW), l
+        assert np.all(np.abs(g[l][1] - gb) <= egb), l
+        print(f"  batch layer {l}: max |gpu - ref| / bound {np.max(np.abs(g[l][0] - gW) / egW):.3f}, "
+              f"median bound / max |dW| {np.median(egW) / np.max(np.abs(gW)):.1e}", flush=True)
+    # end to end against the oracle network (context: the rounding of every operand to BF16)
+    g_flat = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in g])
+    assert rel(g_flat, omlp.gradients(params, WIDTHS, X, Y, mb.bf16)) < 2e-3
+    assert rel(g_flat, omlp.gradients(params, WIDTHS, X, Y)) < 3e-2
     assert abs(loss - omlp.loss(params, WIDTHS, X, Y)) < 3e-2 * omlp.loss(params, WIDTHS, X, Y)
     # deterministic: the same call gives the same bits
-    loss2, g2 = net.gradients(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda())
-    assert loss2 == loss and np.array_equal(g2, g)
+    loss2, g2 = net.gradients(Xd, Yd)
+    assert loss2 == loss and np.array_equal(_unpack_grads(g2)[0][0], g[0][0])
     net.close()
 
 

@@ -16,7 +16,7 @@ from tests.helpers import linf_rel, oracle_sim
 
 pytestmark = pytest.mark.gpu
 
-FIELDS = ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py")
+FIELDS = ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py", "fpx", "fpy")
 
 
 def say(*a):

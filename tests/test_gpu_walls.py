@@ -50,7 +50,7 @@ def test_walls_parity_two_bodies(kernel):
         g.step(n)
         r.run(n)
         gf, of = g.fields(), r.observe()
-        errs = {k: linf_rel(gf[k], of[k]) for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py")}
+        errs = {k: linf_rel(gf[k], of[k]) for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py", "fpx", "fpy")}
         say(f" t={r.t}", {k: f"{v:.1e}" for k, v in errs.items()})
         for k, e in errs.items():
             assert e <= 1e-4, (k, e)
@@ -85,7 +85,7 @@ def test_trap_protocol_parity(walls):
         g.step(n)
         r.run(n)
         gf, of = g.fields(), r.observe()
-        errs = {k: linf_rel(gf[k], of[k]) for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py")}
+        errs = {k: linf_rel(gf[k], of[k]) for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py", "fpx", "fpy")}
         say(f" t={r.t}", {k: f"{v:.1e}" for k, v in errs.items()})
         for k, e in errs.items():
             assert e <= 1e-4, (k, e)
@@ -114,7 +114,7 @@ def test_box_trap_parity(kernel):
         g.step(n)
         r.run(n)
         gf, of = g.fields(), r.observe()
-        errs = {k: linf_rel(gf[k], of[k]) for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py")}
+        errs = {k: linf_rel(gf[k], of[k]) for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py", "fpx", "fpy")}
         say(f" t={r.t}", {k: f"{v:.1e}" for k, v in errs.items()})
         for k, e in errs.items():
             assert e <= 1e-4, (k, e)
@@ -133,7 +133,7 @@ def test_paper_case_parity(fe_units):
     g.step(400)
     r.run(400)
     gf, of = g.fields(), r.observe()
-    errs = {k: linf_rel(gf[k], of[k]) for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py")}
+    errs = {k: linf_rel(gf[k], of[k]) for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py", "fpx", "fpy")}
     say("  ", {k: f"{v:.1e}" for k, v in errs.items()})
     for k, e in errs.items():
         assert e <= 1e-4, (k, e)
@@ -151,7 +151,7 @@ def test_paper_scalar_case_parity():
     g.step(600)
     r.run(600)
     gf, of = g.fields(), r.observe()
-    errs = {k: linf_rel(gf[k], of[k]) for k in ("vx", "vy", "sxx", "syy", "sxy")}
+    errs = {k: linf_rel(gf[k], of[k]) for k in ("vx", "vy", "sxx", "syy", "sxy", "fpx", "fpy")}
     say("  ", {k: f"{v:.1e}" for k, v in errs.items()})
     for k, e in errs.items():
         assert e <= 1e-4, (k, e)
@@ -170,7 +170,7 @@ def test_paper_case_parity_4000_steps():
         g.step(n)
         r.run(n)
         gf, of = g.fields(), r.observe()
-        errs = {k: linf_rel(gf[k], of[k]) for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py")}
+        errs = {k: linf_rel(gf[k], of[k]) for k in ("vx", "vy", "sxx", "syy", "sxy", "Px", "Py", "fpx", "fpy")}
         say(f" t={r.t}", {k: f"{v:.1e}" for k, v in errs.items()})
         for k, e in errs.items():
             assert e <= 1e-4, (k, e)

@@ -180,6 +180,81 @@ def test_area_force_of_a_uniform_divergence_is_divergence_times_area():
     assert abs(F[0] - 2e-4 * area) < 1e-15 * area and abs(F[1]) < 1e-18
 
 
+# --- site-sum restoring force (Sec. III, Fig. 6: div sigma^p summed over the body) -----------
+
+# sigma_xx = a x + d y, sigma_yy = e x + c y, sigma_xy = g x + b y: by central differences
+# div sigma = (d_x sxx + d_y sxy, d_x sxy + d_y syy) = (a + b, g + c) at every site away from the
+# periodic seams; d and e enter neither component, so a transposed derivative shows up.
+_LIN = dict(a=3e-4, b=-1e-4, c=7e-5, d=5e-4, e=-6e-4, g=2e-5)
+
+
+def _general_linear_sigma(nx, ny):
+    x = np.arange(nx)[None, :].astype(float)
+    y = np.arange(ny)[:, None].astype(float)
+    s = np.zeros((3, ny, nx))
+    s[0] = _LIN["a"] * x + _LIN["d"] * y
+    s[1] = _LIN["e"] * x + _LIN["c"] * y
+    s[2] = _LIN["g"] * x + _LIN["b"] * y
+    return s
+
+
+def _winding_count(P):
+    """Lattice points strictly inside the polygon P by the winding number (sum of the signed
+    angles the edges subtend), a test written independently of the crossing rule; only valid
+    when no lattice point lies on the outline."""
+    xs = np.arange(int(np.floor(P[:, 0].min())) - 1, int(np.ceil(P[:, 0].max())) + 2)
+    ys = np.arange(int(np.floor(P[:, 1].min())) - 1, int(np.ceil(P[:, 1].max())) + 2)
+    X, Y = np.meshgrid(xs.astype(float), ys.astype(float))
+    total = np.zeros(X.shape)
+    for i in range(len(P)):
+        ax, ay = P[i - 1, 0] - X, P[i - 1, 1] - Y
+        bx, by = P[i, 0] - X, P[i, 1] - Y
+        total += np.arctan2(ax * by - ay * bx, ax * bx + ay * by)
+    return int(np.sum(np.abs(total) > math.pi))
+
+
+@pytest.mark.parametrize("shape", ["polygon40", "star", "polygon151"])
+def test_site_sum_force_of_a_uniform_divergence_counts_inside_sites(shape):
+    """With a uniform div sigma, the site-sum restoring force is that divergence times the number of
+    lattice points inside the outline, counted here by winding numbers."""
+    nx, ny = 64, 60
+    P = {"polygon40": oracle.polygon(30.37, 28.81, 6.0, 40),
+         "star": _star(11, c=(31.3, 29.45)),
+         "polygon151": oracle.polygon(31.71, 30.13, 24.0, 151)}[shape]
+    n_in = _winding_count(P)
+    assert n_in > 50
+    for orient in (1, -1):   # the count does not depend on the direction the nodes run
+        Q = P[::orient].copy()
+        sim = oracle.Sim(dict(nx=nx, ny=ny), bodies=[oracle.Body(R=Q)], sigma=_general_linear_sigma(nx, ny))
+        F = sim.body_force(0)
+        assert abs(F[0] - (_LIN["a"] + _LIN["b"]) * n_in) <= 1e-15 * n_in
+        assert abs(F[1] - (_LIN["g"] + _LIN["c"]) * n_in) <= 1e-15 * n_in
+        assert np.allclose(F[2:], Q.mean(axis=0), rtol=0, atol=1e-12)
+
+
+def test_site_sum_force_half_open_outline_on_lattice_points():
+    """Outlines through lattice points follow the half-open rule (a point on a left or lower edge is
+    inside, on a right or upper edge outside), so translates of a shape tile the lattice with every
+    point counted once:
+    * the square with corners at x = 10.5, 20.5 and y = 10, 20 (its lower and upper edges run along
+      lattice rows) holds rows y = 10 .. 19 and columns x = 11 .. 20: 100 points;
+    * the diamond |x - 20| + |y - 20| <= 10 (nodes on lattice points) holds, in row y = 20 + d,
+      x from 20 - (10 - |d|) up to but excluding 20 + (10 - |d|), i.e. 2 (10 - |d|) points for
+      |d| < 10 and none in rows 10 and 30: 200 points, its area."""
+    nx = ny = 48
+    square = np.array([[10.5, 10.0], [20.5, 10.0], [20.5, 20.0], [10.5, 20.0]])
+    diamond = np.array([[20.0, 10.0], [30.0, 20.0], [20.0, 30.0], [10.0, 20.0]])
+    # the diamond again with extra nodes along its edges, two of them on lattice points
+    dense = np.concatenate([np.linspace(diamond[i], diamond[(i + 1) % 4], 5, endpoint=False) for i in range(4)])
+    for P, expect in ((square, 100), (diamond, 200), (dense, 200)):
+        for orient in (1, -1):
+            Q = P[::orient].copy()
+            sim = oracle.Sim(dict(nx=nx, ny=ny), bodies=[oracle.Body(R=Q)], sigma=_general_linear_sigma(nx, ny))
+            F = sim.body_force(0)
+            assert abs(F[0] - (_LIN["a"] + _LIN["b"]) * expect) <= 1e-15 * expect, (len(P), orient, F[0])
+            assert abs(F[1] - (_LIN["g"] + _LIN["c"]) * expect) <= 1e-15 * expect, (len(P), orient, F[1])
+
+
 def test_area_force_is_continuous_in_the_nodes_unlike_the_site_sum():
     rng = np.random.default_rng(9)
     sig = rng.standard_normal((3, 40, 40)) * 1e-3
