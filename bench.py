@@ -508,7 +508,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f16-storage/f32" if precision == 1 else "f32 (P in f64)",
+        "dtype": "f16-storage/f32" if precision == 1 else "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "sites": sites,
                    "kernel": "fused" if args.kernel == 0 else "multipass", "graph_chunk": args.graph_chunk,

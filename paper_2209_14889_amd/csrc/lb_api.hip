@@ -363,12 +363,13 @@ Plan make_plan(const lb_sim_params *sims, int n_sims, const Opt &o) {
         sp.oH1 = a.take(9 * sp.N * hb);
         sp.oS0 = a.take(3 * sp.N * 4);
         sp.oS1 = a.take(3 * sp.N * 4);
-        sp.oP0 = a.take(2 * sp.N * 8);
-        sp.oP1 = a.take(2 * sp.N * 8);
+        const size_t pb = o.precision == 1 ? 4 : 8;   // polarization: FP32 offsets with FP16 populations
+        sp.oP0 = a.take(2 * sp.N * pb);
+        sp.oP1 = a.take(2 * sp.N * pb);
         sp.oSE = a.take(4 * sp.N * 4);
         sp.oV = a.take(o.kernel == 1 ? 2 * sp.N * 4 : 0);
         sp.oSP = a.take(o.kernel == 1 ? 3 * sp.N * 4 : 0);
-        sp.oSPP = a.take(o.kernel == 1 ? 2 * sp.N * 8 : 0);
+        sp.oSPP = a.take(o.kernel == 1 ? 2 * sp.N * pb : 0);
         sp.tab = (int)(std::find(pl.clamps.begin(), pl.clamps.end(), p.P_clamp) - pl.clamps.begin());
         sp.blk0 = nblk_sites;
         sp.nblk = (int)((sp.N + 255) / 256);
@@ -416,19 +417,22 @@ Plan make_plan(const lb_sim_params *sims, int n_sims, const Opt &o) {
     return pl;
 }
 
-// strips of at most T-8 columns (nearly equal widths) and segments of about seg rows
+// Work items: a lattice no wider than T is one full-width strip (no halo lanes); a wider one is cut
+// into strips of T-8 columns and one narrower remainder, so only the remainder's block carries
+// idle lanes; segments of about seg rows.
 std::vector<WorkItem> build_items(const std::vector<SimPlan> &sims, int T, int seg) {
     std::vector<WorkItem> items;
     const int W = T - 2 * kHalo;
     for (size_t s = 0; s < sims.size(); ++s) {
         int nx = sims[s].nx, ny = sims[s].ny;
-        int ns = (nx + W - 1) / W;
+        const bool full = nx <= T;
+        int ns = full ? 1 : (nx + W - 1) / W;
         int ng = std::max(1, (ny + seg - 1) / seg);
         for (int g = 0; g < ng; ++g) {
             int y0 = (int)((long)g * ny / ng), y1 = (int)((long)(g + 1) * ny / ng);
             for (int k = 0; k < ns; ++k) {
-                int x0 = (int)((long)k * nx / ns), x1 = (int)((long)(k + 1) * nx / ns);
-                items.push_back(WorkItem{(int)s, x0, y0, x1 - x0, y1 - y0, 0, 0, 0});
+                int x0 = full ? 0 : k * W, x1 = full ? nx : std::min(nx, (k + 1) * W);
+                items.push_back(WorkItem{(int)s, x0, y0, x1 - x0, y1 - y0, full ? 1 : 0, 0, 0});
             }
         }
     }
@@ -957,23 +961,53 @@ static int create_impl(const lb_sim_params *sims, int n_sims, const lb_options *
         d.h[1] = A.ptr<void>(sp.oH1);
         d.sig[0] = A.ptr<float>(sp.oS0);
         d.sig[1] = A.ptr<float>(sp.oS1);
-        d.P[0] = A.ptr<double>(sp.oP0);
-        d.P[1] = A.ptr<double>(sp.oP1);
+        d.P[0] = A.ptr<void>(sp.oP0);
+        d.P[1] = A.ptr<void>(sp.oP1);
         d.sE = A.ptr<float>(sp.oSE);
         d.v = o.kernel == 1 ? A.ptr<float>(sp.oV) : nullptr;
         d.sps = o.kernel == 1 ? A.ptr<float>(sp.oSP) : nullptr;
-        d.spp = o.kernel == 1 ? A.ptr<double>(sp.oSPP) : nullptr;
+        d.spp = o.kernel == 1 ? A.ptr<void>(sp.oSPP) : nullptr;
+        // P: with FP16 populations FP32 offsets from the mean of the initial field (rounded to FP32);
+        // with FP32 populations the FP64 values themselves (reference 0)
+        {
+            double m0 = 0.0, m1 = 0.0;
+            if (p.init_P && fp16) {
+                for (size_t i = 0; i < N; ++i) {
+                    m0 += p.init_P[i];
+                    m1 += p.init_P[N + i];
+                }
+                m0 /= (double)N;
+                m1 /= (double)N;
+            }
+            d.pref[0] = (float)m0;
+            d.pref[1] = (float)m1;
+            const double r0 = d.pref[0], r1 = d.pref[1];
+            d.pref_d[0] = r0;
+            d.pref_d[1] = r1;
+            d.alpha_d = p.alpha;
+            d.beta_d = p.beta;
+            if (p.init_P)
+                for (size_t i = 0; i < 2 * N; ++i) h->any_pol = h->any_pol || p.init_P[i] != 0.0;
+            if (fp16) {
+                std::vector<float> pb(2 * N, 0.0f);
+                HIPCHK(hipMemcpyAsync(d.P[1], pb.data(), 2 * N * 4, hipMemcpyHostToDevice, h->stream));
+                if (p.init_P)
+                    for (size_t i = 0; i < N; ++i) {
+                        pb[i] = (float)(p.init_P[i] - r0);
+                        pb[N + i] = (float)(p.init_P[N + i] - r1);
+                    }
+                HIPCHK(hipMemcpyAsync(d.P[0], pb.data(), 2 * N * 4, hipMemcpyHostToDevice, h->stream));
+                HIPCHK(hipStreamSynchronize(h->stream));
+            } else {
+                std::vector<double> pb(2 * N, 0.0);
+                HIPCHK(hipMemcpyAsync(d.P[1], pb.data(), 2 * N * 8, hipMemcpyHostToDevice, h->stream));
+                if (p.init_P) std::copy(p.init_P, p.init_P + 2 * N, pb.begin());
+                HIPCHK(hipMemcpyAsync(d.P[0], pb.data(), 2 * N * 8, hipMemcpyHostToDevice, h->stream));
+                HIPCHK(hipStreamSynchronize(h->stream));
+            }
+        }
         h->hs.push_back(d);
 
-        // P (FP64) and sigma
-        {
-            std::vector<double> pb(2 * N, 0.0);
-            HIPCHK(hipMemcpyAsync(d.P[1], pb.data(), 2 * N * 8, hipMemcpyHostToDevice, h->stream));
-            if (p.init_P) std::copy(p.init_P, p.init_P + 2 * N, pb.begin());
-            HIPCHK(hipMemcpyAsync(d.P[0], pb.data(), 2 * N * 8, hipMemcpyHostToDevice, h->stream));
-            HIPCHK(hipStreamSynchronize(h->stream));
-            for (double v : pb) h->any_pol = h->any_pol || v != 0.0;
-        }
         buf.assign(3 * N, 0.0f);
         if (p.init_sigma)
             for (size_t i = 0; i < 3 * N; ++i) buf[i] = (float)p.init_sigma[i];
@@ -1297,7 +1331,8 @@ int lb_body_forces_device(lb_handle *h, double *device_out, size_t n_out) {
 int lb_state_bytes(lb_handle *h, double *bytes_per_site) {
     if (!h || !bytes_per_site) return fail(LB_EINVAL, "NULL argument");
     const double pop = h->opt.precision == 1 ? 2.0 : 4.0;
-    *bytes_per_site = 2.0 * (9.0 * pop + 3.0 * 4.0 + 2.0 * (double)sizeof(*h->hs[0].P[0]));
+    const double pol = h->opt.precision == 1 ? 4.0 : 8.0;
+    *bytes_per_site = 2.0 * (9.0 * pop + 3.0 * 4.0 + 2.0 * pol);
     return LB_OK;
 }
 

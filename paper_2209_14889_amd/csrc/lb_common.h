@@ -39,12 +39,16 @@ struct SimDev {
     const float *tab;               // per segment 8 floats: cubics in the local coordinate of A2 = a2/s, A4 = a4/s^2
     void *h[2];                     // post-collision population offsets, 9 planes (float or half)
     float *sig[2];                  // polymer stress planes sxx, syy, sxy
-    double *P[2];                   // polarization planes Px, Py; FP64 because its per-step
-                                    // increments fall below the FP32 resolution of |P| ~ 1
+    void *P[2];                     // polarization planes, offsets Px - pref[0], Py - pref[1]: FP32
+                                    // with FP16 populations, FP64 (pref = 0) with FP32 populations
+    float pref[2];                  // reference polarization the offsets are taken from (FP32 form:
+                                    // the mean of the initial field, rounded to FP32)
+    double pref_d[2];               // the same in FP64, and alpha, beta in FP64 (the slope of the
+    double alpha_d, beta_d;         // molecular field)
     float *sE;                      // scratch: Ericksen stress xx, xy, yx, yy
     float *v;                       // multi-pass scratch: velocity
     float *sps;                     // multi-pass scratch: predicted stress (3 planes)
-    double *spp;                    // multi-pass scratch: predicted polarization (2 planes)
+    void *spp;                      // multi-pass scratch: predicted polarization offsets (2 planes)
 };
 
 struct BodyDev {
@@ -61,9 +65,10 @@ struct BodyDev {
     int *nix;                       // per node: first footprint site (unwrapped x, y)
 };
 
-// fused kernel work item: columns [x0, x0+w), rows [y0, y0+l) of one simulation
+// fused kernel work item: columns [x0, x0+w), rows [y0, y0+l) of one simulation; full: the strip
+// is the whole lattice width (x0 = 0, w = nx), its lanes' neighbours wrap within it
 struct WorkItem {
-    int sim, x0, y0, w, l, pad0, pad1, pad2;
+    int sim, x0, y0, w, l, full, pad1, pad2;
 };
 
 // multi-pass kernels: one 256-site block of one simulation

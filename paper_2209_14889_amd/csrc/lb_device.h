@@ -43,6 +43,33 @@ template <typename T> __device__ __forceinline__ LBK_GLOBAL T *at32(T *base, uns
     return (LBK_GLOBAL T *)((LBK_GLOBAL char *)base + i * (unsigned)sizeof(T));
 }
 
+// Raw buffer access to a state array: a buffer resource over its base (no stride, the whole 32-bit
+// range, the gfx9 raw-buffer format word), a lane's byte offset (its column) in the vector offset
+// and the uniform part (plane and row) in the scalar offset, so a load or store costs no vector
+// arithmetic.  Every state array of one simulation is < 4 GiB, so both offsets fit 32 bits.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t state_rsrc(const void *p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)0xffffffff, 0x00020000);
+}
+__device__ __forceinline__ float buf_ldf(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void buf_stf(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float &v) {
+    v = buf_ldf(r, voff, soff);
+}
+__device__ __forceinline__ void buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double &v) {
+    v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
+    buf_stf(r, voff, soff, v);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double v) {
+    typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)) B64;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B64, v), r, (int)voff, (int)soff, 0);
+}
+
 // Raw: the stored word, fetched one iteration ahead and converted only when used, so a prefetch
 // does not wait for its own load.
 template <> struct Pop<float> {
@@ -56,6 +83,12 @@ template <> struct Pop<float> {
     // the stored value as is (for FP16 storage: still times the 2^S scale)
     static __device__ __forceinline__ float cvt_stored(Raw r) { return r; }
     static __device__ __forceinline__ void st_stored(float *p, unsigned i, float v) { *at32(p, i) = v; }
+    static __device__ __forceinline__ Raw ld_buf(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+        return buf_ldf(r, voff, soff);
+    }
+    static __device__ __forceinline__ void st_buf(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
+        buf_stf(r, voff, soff, v);
+    }
     static constexpr bool kScaled = false;
 };
 template <> struct Pop<__half> {
@@ -82,6 +115,12 @@ template <> struct Pop<__half> {
     static __device__ __forceinline__ float cvt_stored(Raw r) { return __half2float(__ushort_as_half((unsigned short)r)); }
     static __device__ __forceinline__ void st_stored(__half *p, unsigned i, float v) {
         *at32(reinterpret_cast<unsigned short *>(p), i) = __half_as_ushort(__float2half_rn(v));
+    }
+    static __device__ __forceinline__ Raw ld_buf(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+        return (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+    }
+    static __device__ __forceinline__ void st_buf(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, (int)voff, (int)soff, 0);
     }
     static constexpr bool kScaled = true;
 };
@@ -156,7 +195,7 @@ __device__ __forceinline__ Stiff stiffness(const SimDev &S, Tab tab, float Px, f
         A2 = fmaf(fmaf(fmaf(a.w, t, a.z), t, a.y), t, a.x);
         A4 = fmaf(fmaf(fmaf(b.w, t, b.z), t, b.y), t, b.x);
     } else {
-        float r = S.smax / s;
+        float r = S.smax * __builtin_amdgcn_rcpf(s);   // s >= smax > 0
         A2 = S.A2max * r;
         A4 = S.A4max * r * r;
     }
@@ -223,23 +262,35 @@ __device__ __forceinline__ void rhs_sigma(const SimDev &S, const Stiff &k, const
     }
 }
 
-// The polarization is FP64 state.  Its right-hand side and the Ericksen stress take the
-// cancelling quantities in FP64 (the slope a = alpha + beta |Y|^2, a small difference of O(1)
-// numbers near the equilibrium magnitude, and the neighbour-minus-centre differences) and the
-// rest in FP32: rounding the values themselves to FP32 would leave a fixed grid-scale pattern of
-// 3e-8 whose Laplacian, through kappa and the Ericksen stress, drives a spurious flow.
+// Polarization storage follows the population storage.  With FP32 populations (the full-precision
+// form, bar 1e-4) P is FP64 state: its per-step increments can fall far below the FP32
+// resolution of |P| ~ 1, and FP32 state rounding (3e-8 per step) feeds the molecular field a
+// site-to-site noise that, through the Ericksen stress, measurably moves weak flows.  With FP16
+// populations (the reduced-precision form, bar 1e-3) P is stored as FP32 offsets Y = P - pref
+// from a per-simulation reference (the mean of the initial field), which keeps near-uniform
+// director fields' offsets small and their increments resolved.  PT is the storage type; the FP64
+// form takes pref = 0.
+template <typename HT> struct PolOf { typedef double T; };
+template <> struct PolOf<__half> { typedef float T; };
+
+// Local quantities of eqBE and the Ericksen stress from the stored values.  The slope
+// a = alpha + beta |P|^2 cancels to near zero at the equilibrium magnitude, so it is formed in FP64
+// from the exact value pref + Y; the neighbour differences are formed in the storage precision
+// (exact for FP64, exact for FP32 offsets of close neighbours) and the rest in FP32.
 struct PLocal {
-    float c[2];      // centre
+    float c[2];      // centre P = pref + Y
     float d[4][2];   // e, w, n, s minus the centre
-    float a;         // alpha + beta |Y|^2
+    float a;         // alpha + beta |P|^2
 };
-__device__ __forceinline__ PLocal p_local(const SimDev &S, const double Y[2], const double Ye[2], const double Yw[2],
-                                          const double Yn[2], const double Ys[2]) {
+template <typename PT>
+__device__ __forceinline__ PLocal p_local(const SimDev &S, const PT Y[2], const PT Ye[2], const PT Yw[2],
+                                          const PT Yn[2], const PT Ys[2]) {
     PLocal L;
-    L.a = (float)((double)S.alpha + (double)S.beta * (Y[0] * Y[0] + Y[1] * Y[1]));
+    const double P0 = S.pref_d[0] + (double)Y[0], P1 = S.pref_d[1] + (double)Y[1];
+    L.a = (float)fma(S.beta_d, fma(P0, P0, P1 * P1), S.alpha_d);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        L.c[q] = (float)Y[q];
+        L.c[q] = (float)((PT)S.pref[q] + Y[q]);
         L.d[0][q] = (float)(Ye[q] - Y[q]);
         L.d[1][q] = (float)(Yw[q] - Y[q]);
         L.d[2][q] = (float)(Yn[q] - Y[q]);
@@ -248,12 +299,11 @@ __device__ __forceinline__ PLocal p_local(const SimDev &S, const double Y[2], co
     return L;
 }
 
-// right-hand side of eqBE: -(v.grad)Y - Omega Y + xi Psi Y - Gamma h(Y),
-// h = (alpha + beta |Y|^2) Y - kappa lap Y.  The state Y and the Heun sums stay FP64 (per-step
-// increments of Y are far below the FP32 resolution of |Y|).
-__device__ __forceinline__ void rhs_P(const SimDev &S, const Grad &g, float ux, float uy,
-                                      const double Y[2], const double Ye[2], const double Yw[2],
-                                      const double Yn[2], const double Ys[2], double R[2]) {
+// right-hand side of eqBE for the stored offsets: -(v.grad)Y - Omega P + xi Psi P - Gamma h(P),
+// h = (alpha + beta |P|^2) P - kappa lap P (pref is constant, so the gradients of P are those of Y)
+template <typename PT>
+__device__ __forceinline__ void rhs_P(const SimDev &S, const Grad &g, float ux, float uy, const PT Y[2],
+                                      const PT Ye[2], const PT Yw[2], const PT Yn[2], const PT Ys[2], PT R[2]) {
     const PLocal L = p_local(S, Y, Ye, Yw, Yn, Ys);
     const float lap0 = (L.d[0][0] + L.d[1][0]) + (L.d[2][0] + L.d[3][0]);
     const float lap1 = (L.d[0][1] + L.d[1][1]) + (L.d[2][1] + L.d[3][1]);
@@ -261,14 +311,15 @@ __device__ __forceinline__ void rhs_P(const SimDev &S, const Grad &g, float ux, 
     const float h1 = L.a * L.c[1] - S.kappa * lap1;
     const float adv0 = ux * (0.5f * (L.d[0][0] - L.d[1][0])) + uy * (0.5f * (L.d[2][0] - L.d[3][0]));
     const float adv1 = ux * (0.5f * (L.d[0][1] - L.d[1][1])) + uy * (0.5f * (L.d[2][1] - L.d[3][1]));
-    R[0] = (double)(-adv0 - g.om * L.c[1] + S.xi * (g.psi0 * L.c[0] + g.psi2 * L.c[1]) - S.Gamma * h0);
-    R[1] = (double)(-adv1 + g.om * L.c[0] + S.xi * (g.psi2 * L.c[0] + g.psi1 * L.c[1]) - S.Gamma * h1);
+    R[0] = (PT)(-adv0 - g.om * L.c[1] + S.xi * (g.psi0 * L.c[0] + g.psi2 * L.c[1]) - S.Gamma * h0);
+    R[1] = (PT)(-adv1 + g.om * L.c[0] + S.xi * (g.psi2 * L.c[0] + g.psi1 * L.c[1]) - S.Gamma * h1);
 }
 
-// Ericksen stress at a site (Sec. II C 1, with kappa on the gradient term), from FP64 P:
-// out = (xx, xy, yx, yy)
-__device__ __forceinline__ void ericksen(const SimDev &S, const double P[2], const double Pe[2], const double Pw[2],
-                                         const double Pn[2], const double Ps[2], float E[4]) {
+// Ericksen stress at a site (Sec. II C 1, with kappa on the gradient term), from the stored
+// values: out = (xx, xy, yx, yy)
+template <typename PT>
+__device__ __forceinline__ void ericksen(const SimDev &S, const PT P[2], const PT Pe[2], const PT Pw[2],
+                                         const PT Pn[2], const PT Ps[2], float E[4]) {
     const PLocal L = p_local(S, P, Pe, Pw, Pn, Ps);
     const float kap = S.kappa, xi = S.xi, P0 = L.c[0], P1 = L.c[1];
     const float lap0 = (L.d[0][0] + L.d[1][0]) + (L.d[2][0] + L.d[3][0]);

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <hip/hip_fp16.h>
 
 #include "lb_device.h"
@@ -29,16 +30,21 @@ namespace lbk {
 // immersed boundary
 // ------------------------------------------------------------------------------------------------
 
-// the four x (or y) weights phi(R - i), i = floor(R) - 1 .. floor(R) + 2, of the cosine kernel;
-// FP32 is enough for weights of values that are themselves FP32
+// the four x (or y) weights phi(R - i), i = floor(R) - 1 .. floor(R) + 2, of the cosine kernel
+// phi(r) = (1 + cos(pi r / 2)) / 4 (App. A).  With f = R - floor(R) in [0, 1) the four distances
+// are 1 + f, f, f - 1, f - 2, whose cosines are -sin, cos, sin, -cos of pi f / 2: one sincos
+// gives all four (the last weight is 0 at f = 0, where its site leaves the support |r| < 2).
+// FP32 is enough for weights of values that are themselves FP32.
 __device__ __forceinline__ void phi4(double R, int &i0, float w[4]) {
-    i0 = (int)floor(R) - 1;
-    float fr = (float)(R - (double)i0);   // distance to the first site, in [1, 2)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        float r = fr - (float)k;
-        w[k] = fabsf(r) < 2.0f ? 0.25f * (1.0f + cosf(1.57079632679f * r)) : 0.0f;
-    }
+    const double fl = floor(R);
+    i0 = (int)fl - 1;
+    const float f = (float)(R - fl);
+    float sn, cs;
+    sincosf(1.57079632679f * f, &sn, &cs);
+    w[0] = 0.25f * (1.0f - sn);
+    w[1] = 0.25f * (1.0f + cs);
+    w[2] = 0.25f * (1.0f + sn);
+    w[3] = 0.25f * (1.0f - cs);
 }
 
 __device__ __forceinline__ double pull_factor(const BodyDev &B, double t) {
@@ -507,18 +513,19 @@ __device__ __forceinline__ void inc_row(unsigned &r, unsigned ny) { r = (r + 1u 
 // polarization right-hand side is proportional to P), so the Ericksen stress vanishes and C~ is
 // its isotropic value: the scalar model of Sec. II B.  That variant skips all P work.
 template <int T, typename HT, bool WALLS, bool POL>
-__global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, const BodyDev *__restrict__ bodies,
+__global__ __launch_bounds__(T, (WALLS || !std::is_same<HT, __half>::value) ? 3 : 4) void k_fused(const SimDev *__restrict__ sims, const BodyDev *__restrict__ bodies,
                                              const WorkItem *__restrict__ items, int n_items, int cur,
                                              int *__restrict__ d_t) {
     // row-exchange rings; values a thread needs only from its own column one row below live in
     // registers (the "carried" row of the previous iteration)
+    typedef typename PolOf<HT>::T PT;   // polarization storage: FP32 offsets with FP16 populations, else FP64
     constexpr int TP = POL ? T : 1;   // the P rings exist only in the variant with P
-    __shared__ double rP[4][2][TP];   // polarization rows f-3 .. f
+    __shared__ PT rP[4][2][TP];       // polarization, rows f-3 .. f
     __shared__ float rS[3][3][T];     // stress rows f-3 .. f-1
     __shared__ float rE[2][2][TP];    // Ericksen xx and yx, rows f-2 .. f-1
     __shared__ float rV[2][2][T];     // velocity rows f-3 .. f-2
     __shared__ float rQs[2][3][T];    // predicted stress rows f-4 .. f-3
-    __shared__ double rQp[2][2][TP];  // predicted polarization rows f-4 .. f-3
+    __shared__ PT rQp[2][2][TP];      // predicted polarization, rows f-4 .. f-3
     __shared__ float4 sTab[2 * kStiffSeg];     // stiffness cubics of the item's simulation
     __shared__ ItemBody sIB[kItemBodies];      // bodies whose patches touch the item
     __shared__ int sNB;                        // their number, -1 if more than kItemBodies
@@ -536,16 +543,23 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
         HT *__restrict__ hout = reinterpret_cast<HT *>(S.h[nxt]);
         const float *__restrict__ sgi = S.sig[cur];
         float *__restrict__ sgo = S.sig[nxt];
-        const double *__restrict__ Pi = S.P[cur];
-        double *__restrict__ Po = S.P[nxt];
-        const int c = wi.x0 - kHalo + tid;
+        const PT *__restrict__ Pi = static_cast<const PT *>(S.P[cur]);
+        PT *__restrict__ Po = static_cast<PT *>(S.P[nxt]);
+        // A strip of w columns takes lanes 0 .. w+7: 4 halo columns on each side, recomputed by
+        // the neighbouring strip.  A lattice no wider than the work-group is one full-width strip
+        // (wi.full): lane = column, no halo lanes, and a lane's east and west neighbours wrap
+        // around within the strip.  Lanes beyond the strip idle (whole waves skip every stage).
+        const bool full = wi.full != 0;
+        const int lanes = full ? wi.w : wi.w + 2 * kHalo;
+        const bool live = tid < lanes;
+        const int c = full ? (live ? tid : 0) : wi.x0 - kHalo + tid;
         const unsigned x = (unsigned)wrapi(c, (int)nx), xm = (unsigned)wrapi(c - 1, (int)nx),
                        xp = (unsigned)wrapi(c + 1, (int)nx);
         const int wcol = wi.w;
-        const bool colB = tid >= 1 && tid < wcol + 7;
-        const bool colC = tid >= 2 && tid < wcol + 6;
-        const bool colD = tid >= 3 && tid < wcol + 5;
-        const bool colE = tid >= 4 && tid < wcol + 4;
+        const bool colB = full ? live : tid >= 1 && tid < wcol + 7;
+        const bool colC = full ? live : tid >= 2 && tid < wcol + 6;
+        const bool colD = full ? live : tid >= 3 && tid < wcol + 5;
+        const bool colE = full ? live : tid >= 4 && tid < wcol + 4;
         const float is = S.inv_scale, sc = S.scale;
 
         // per-item constants: the stiffness cubics, and the bodies whose patches reach the rows
@@ -562,7 +576,7 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                 ib.ps = B.ps;
                 ib.fib = B.fib;
                 ib.vib = B.vib;
-                hit = ring_overlap(ib.ox, ib.ps, wrapi(wi.x0 - kHalo, (int)nx), wi.w + 2 * kHalo, (int)nx) &&
+                hit = ring_overlap(ib.ox, ib.ps, full ? 0 : wrapi(wi.x0 - kHalo, (int)nx), lanes, (int)nx) &&
                       ring_overlap(ib.oy, ib.ps, wrapi(wi.y0 - 2, (int)ny), wi.l + 4, (int)ny);
             }
             const unsigned long long m = __ballot(hit);
@@ -584,11 +598,22 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
         const unsigned ytop = ny - 1u;
         // closed box: this lane's column is next to the west / east wall
         const bool xw = WALLS && S.walls == 2 && x == 0u, xe = WALLS && S.walls == 2 && x == nx - 1u;
+        // the lanes holding the east and west neighbours (the lane itself beyond a wall: mirror
+        // ghosts; wrapped around a full-width strip)
+        const int te = xe ? tid : (full && tid + 1 == lanes ? 0 : tid + 1);
+        const int tw = xw ? tid : (full && tid == 0 ? lanes - 1 : tid - 1);
+        // this lane's column and its neighbours as byte offsets within a row of populations (HT)
+        // and of the 4-byte stress and polarization planes; the state arrays as buffers
+        const unsigned HB = (unsigned)sizeof(HT);
+        const unsigned bh = x * HB, bhm = xm * HB, bhp = xp * HB;
+        const unsigned b4 = x * 4u, bP = x * (unsigned)sizeof(PT);
+        const __amdgpu_buffer_rsrc_t rHi = state_rsrc(hin), rHo = state_rsrc(hout), rSi = state_rsrc(sgi),
+                                     rSo = state_rsrc(sgo), rPi = state_rsrc(Pi), rPo = state_rsrc(Po);
 
         // Loads for the next iteration, issued one iteration ahead.  Every lane loads (all
         // indices are wrapped into the lattice); lanes outside a stage's columns never use them.
         struct Pre {
-            double P0, P1;                 // P(f+1)
+            PT P0, P1;                     // P(f+1)
             float S0, S1, S2;              // sigma(f)
             typename Pop<HT>::Raw H[9];    // populations pulled into row f-1
         };
@@ -597,23 +622,24 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
         // predicted centre (the next corrector's south neighbour).
         struct Carry {
             float vx, vy, s0, s1, s2;
-            double p0, p1;
+            PT p0, p1;
             Grad g;
             Stiff k;
             float q0, q1, q2;
-            double qp0, qp1;
+            PT qp0, qp1;
         };
         Pre preA, preB;
         Carry carA, carB;
-        {
-            const unsigned iP = r0 * nx + x, iS = rm1 * nx + x;
+        if (live) {
+            const unsigned rP0 = r0 * nx * (unsigned)sizeof(PT), NP = N * (unsigned)sizeof(PT);
+            const unsigned rS0 = rm1 * nx * 4u, N4 = N * 4u;
             if (POL) {
-                preA.P0 = ld32(Pi, iP);
-                preA.P1 = ld32(Pi, N + iP);
+                buf_ld(rPi, bP, rP0, preA.P0);
+                buf_ld(rPi, bP, NP + rP0, preA.P1);
             }
-            preA.S0 = ld32(sgi, iS);
-            preA.S1 = ld32(sgi, N + iS);
-            preA.S2 = ld32(sgi, 2u * N + iS);
+            preA.S0 = buf_ldf(rSi, b4, rS0);
+            preA.S1 = buf_ldf(rSi, b4, N4 + rS0);
+            preA.S2 = buf_ldf(rSi, b4, 2u * N4 + rS0);
         }
         // Ericksen xy, yy of this column at rows f-1, f-2, f-3
         float exy1 = 0.f, eyy1 = 0.f, exy2 = 0.f, eyy2 = 0.f, exy3 = 0.f, eyy3 = 0.f;
@@ -650,16 +676,29 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             for (int q = 0; q < 9; ++q) d[q] = Pop<HT>::cvt_stored(pin.H[q]);   // times the storage scale
             // prefetch for iteration j+1: P(f+1), sigma(f), and the populations pulled into row
             // f-1: h_n(x, r) = h*_n(x - c_n, r - c_n) from rows f-2, f-1, f
-            if (j + 1 < niter) {
-                const unsigned iP = rp1 * nx + x, iS = r0 * nx + x;
+            if (live && j + 1 < niter) {
+                const unsigned rP1 = rp1 * nx * (unsigned)sizeof(PT), NP = N * (unsigned)sizeof(PT);
+                const unsigned rS1 = r0 * nx * 4u, N4 = N * 4u;
                 if (POL) {
-                    pout.P0 = ld32(Pi, iP);
-                    pout.P1 = ld32(Pi, N + iP);
+                    buf_ld(rPi, bP, rP1, pout.P0);
+                    buf_ld(rPi, bP, NP + rP1, pout.P1);
                 }
-                pout.S0 = ld32(sgi, iS);
-                pout.S1 = ld32(sgi, N + iS);
-                pout.S2 = ld32(sgi, 2u * N + iS);
-                if (j + 1 >= 4) {
+                pout.S0 = buf_ldf(rSi, b4, rS1);
+                pout.S1 = buf_ldf(rSi, b4, N4 + rS1);
+                pout.S2 = buf_ldf(rSi, b4, 2u * N4 + rS1);
+                if (!WALLS && j + 1 >= 4) {
+                    // periodic: plane and row in the scalar offset, the column in the lane offset
+                    const unsigned NH = N * HB, yc = rm1 * nx * HB, ym = rm2 * nx * HB, yp = r0 * nx * HB;
+                    pout.H[0] = Pop<HT>::ld_buf(rHi, bh, yc);
+                    pout.H[1] = Pop<HT>::ld_buf(rHi, bhm, NH + yc);
+                    pout.H[2] = Pop<HT>::ld_buf(rHi, bh, 2u * NH + ym);
+                    pout.H[3] = Pop<HT>::ld_buf(rHi, bhp, 3u * NH + yc);
+                    pout.H[4] = Pop<HT>::ld_buf(rHi, bh, 4u * NH + yp);
+                    pout.H[5] = Pop<HT>::ld_buf(rHi, bhm, 5u * NH + ym);
+                    pout.H[6] = Pop<HT>::ld_buf(rHi, bhp, 6u * NH + ym);
+                    pout.H[7] = Pop<HT>::ld_buf(rHi, bhp, 7u * NH + yp);
+                    pout.H[8] = Pop<HT>::ld_buf(rHi, bhm, 8u * NH + yp);
+                } else if (WALLS && j + 1 >= 4) {
                     const unsigned yc = rm1 * nx, ym = rm2 * nx, yp = r0 * nx;
                     // halfway bounce-back: what would come from beyond a wall is the opposite
                     // direction's post-collision value at the same site
@@ -684,11 +723,11 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             eyy2 = eyy1;
             if (POL && j >= 2 && colB) {
                 const int an = walls && rm1 == ytop ? a1 : a0, as = walls && rm1 == 0u ? a1 : a2;
-                double Pc[2] = {rP[a1][0][tid], rP[a1][1][tid]};
-                double Pe[2] = {rP[a1][0][xe ? tid : tid + 1], rP[a1][1][xe ? tid : tid + 1]};
-                double Pw[2] = {rP[a1][0][xw ? tid : tid - 1], rP[a1][1][xw ? tid : tid - 1]};
-                double Pn[2] = {rP[an][0][tid], rP[an][1][tid]};
-                double Ps[2] = {rP[as][0][tid], rP[as][1][tid]};
+                PT Pc[2] = {rP[a1][0][tid], rP[a1][1][tid]};
+                PT Pe[2] = {rP[a1][0][te], rP[a1][1][te]};
+                PT Pw[2] = {rP[a1][0][tw], rP[a1][1][tw]};
+                PT Pn[2] = {rP[an][0][tid], rP[an][1][tid]};
+                PT Ps[2] = {rP[as][0][tid], rP[as][1][tid]};
                 float E[4];
                 ericksen(S, Pc, Pe, Pw, Pn, Ps, E);
                 rE[o1][0][tid] = E[0];
@@ -701,7 +740,6 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             if (j >= 4 && colC) {
                 const bool clo = walls && rm2 == 0u, chi = walls && rm2 == ytop;
                 const int bn = chi ? b2 : b1, bs = clo ? b2 : b3;
-                const int te = xe ? tid : tid + 1, tw = xw ? tid : tid - 1;   // mirror ghosts at x walls
                 float Fx = 0.5f * (rS[b2][0][te] - rS[b2][0][tw]) + 0.5f * (rS[bn][2][tid] - rS[bs][2][tid]);
                 float Fy = 0.5f * (rS[b2][2][te] - rS[b2][2][tw]) + 0.5f * (rS[bn][1][tid] - rS[bs][1][tid]);
                 if (POL && S.ericksen) {
@@ -722,9 +760,9 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                 rV[o0][1][tid] = uy;
                 const int r = wi.y0 + j - 6;   // = f - 2
                 if (colE && r >= wi.y0 && r < wi.y0 + wi.l) {
-                    const unsigned o = rm2 * nx + x;
+                    const unsigned o = rm2 * nx * HB, NH = N * HB;
 #pragma unroll
-                    for (int q = 0; q < 9; ++q) Pop<HT>::st_stored(hout, (unsigned)q * N + o, d[q]);
+                    for (int q = 0; q < 9; ++q) Pop<HT>::st_buf(rHo, bh, (unsigned)q * NH + o, d[q]);
                     if (nib > 0)
                         ib_store_v_list(sIB, nib, (int)nx, (int)ny, (int)x, (int)rm2, ux, uy);
                     else if (nib < 0)
@@ -736,7 +774,7 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             if (j >= 5 && colD) {
                 cout.vx = rV[o1][0][tid];
                 cout.vy = rV[o1][1][tid];
-                double Pc[2] = {POL ? rP[a3][0][tid] : 0.0, POL ? rP[a3][1][tid] : 0.0};
+                PT Pc[2] = {POL ? rP[a3][0][tid] : (PT)0, POL ? rP[a3][1][tid] : (PT)0};
                 float X[3];
 #pragma unroll
                 for (int q = 0; q < 3; ++q) X[q] = rS[b3][q][tid];
@@ -745,12 +783,12 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                     const bool dlo = walls && rm3 == 0u, dhi = walls && rm3 == ytop;
                     const float vxn = dhi ? -cout.vx : rV[o0][0][tid], vyn = dhi ? -cout.vy : rV[o0][1][tid];
                     const float vxs = dlo ? -cout.vx : cin.vx, vys = dlo ? -cout.vy : cin.vy;
-                    const int te = xe ? tid : tid + 1, tw = xw ? tid : tid - 1;
                     const float sxe = xe ? -1.0f : 1.0f, sxw = xw ? -1.0f : 1.0f;   // no-slip ghosts
                     cout.g = grad_v(sxe * rV[o1][0][te], sxw * rV[o1][0][tw], vxn, vxs,
                                     sxe * rV[o1][1][te], sxw * rV[o1][1][tw], vyn, vys);
                     // without P: the isotropic stiffness (all anisotropic parts vanish at P = 0)
-                    cout.k = POL ? stiffness(S, sTab, (float)Pc[0], (float)Pc[1]) : Stiff{0.f, 0.f, 0.f, 0.f};
+                    cout.k = POL ? stiffness(S, sTab, (float)((PT)S.pref[0] + Pc[0]), (float)((PT)S.pref[1] + Pc[1]))
+                                 : Stiff{0.f, 0.f, 0.f, 0.f};
                     float Xe[3], Xw[3], Xn[3], Rs[3];
                     const int bn = dhi ? b3 : b2;
 #pragma unroll
@@ -765,12 +803,12 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                     rQs[o1][1][tid] = X[1] + Rs[1];
                     rQs[o1][2][tid] = X[2] + Rs[2];
                     if (POL) {
-                        double Pe[2] = {rP[a3][0][te], rP[a3][1][te]};
-                        double Pw[2] = {rP[a3][0][tw], rP[a3][1][tw]};
+                        PT Pe[2] = {rP[a3][0][te], rP[a3][1][te]};
+                        PT Pw[2] = {rP[a3][0][tw], rP[a3][1][tw]};
                         const int an = dhi ? a3 : a2;
-                        double Pn[2] = {rP[an][0][tid], rP[an][1][tid]};
-                        double Ps[2] = {dlo ? Pc[0] : cin.p0, dlo ? Pc[1] : cin.p1};
-                        double Rp[2];
+                        PT Pn[2] = {rP[an][0][tid], rP[an][1][tid]};
+                        PT Ps[2] = {dlo ? Pc[0] : cin.p0, dlo ? Pc[1] : cin.p1};
+                        PT Rp[2];
                         rhs_P(S, cout.g, cout.vx, cout.vy, Pc, Pe, Pw, Pn, Ps, Rp);
                         rQp[o1][0][tid] = Pc[0] + Rp[0];
                         rQp[o1][1][tid] = Pc[1] + Rp[1];
@@ -787,15 +825,14 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
             // from j = 7 it records the predicted centre values as next iteration's south row
             if (j >= 7 && colE) {
                 float X[3], Xe[3], Xw[3], Xn[3], Rs[3];
-                double Y[2], Ye[2], Yw[2], Yn[2], Rp[2];
+                PT Y[2], Ye[2], Yw[2], Yn[2], Rp[2];
 #pragma unroll
                 for (int q = 0; q < 3; ++q) X[q] = rQs[o0][q][tid];
-                Y[0] = POL ? rQp[o0][0][tid] : 0.0;
-                Y[1] = POL ? rQp[o0][1][tid] : 0.0;
+                Y[0] = POL ? rQp[o0][0][tid] : (PT)0;
+                Y[1] = POL ? rQp[o0][1][tid] : (PT)0;
                 if (j >= 8) {
                     const bool elo = walls && rm4 == 0u, ehi = walls && rm4 == ytop;
                     const int on = ehi ? o0 : o1;
-                    const int te = xe ? tid : tid + 1, tw = xw ? tid : tid - 1;
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
                         Xe[q] = rQs[o0][q][te];
@@ -804,10 +841,10 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                     }
                     const float Xs[3] = {elo ? X[0] : cin.q0, elo ? X[1] : cin.q1, elo ? X[2] : cin.q2};
                     rhs_sigma(S, cin.k, cin.g, cin.vx, cin.vy, X, Xe, Xw, Xn, Xs, Rs);
-                    const unsigned o = rm4 * nx + x;
-                    st32(sgo, o, 0.5f * ((cin.s0 + X[0]) + Rs[0]));
-                    st32(sgo, N + o, 0.5f * ((cin.s1 + X[1]) + Rs[1]));
-                    st32(sgo, 2u * N + o, 0.5f * ((cin.s2 + X[2]) + Rs[2]));
+                    const unsigned o = rm4 * nx * 4u, N4 = N * 4u;
+                    buf_stf(rSo, b4, o, 0.5f * ((cin.s0 + X[0]) + Rs[0]));
+                    buf_stf(rSo, b4, N4 + o, 0.5f * ((cin.s1 + X[1]) + Rs[1]));
+                    buf_stf(rSo, b4, 2u * N4 + o, 0.5f * ((cin.s2 + X[2]) + Rs[2]));
                     if (POL) {   // without P both P buffers stay zero
 #pragma unroll
                         for (int q = 0; q < 2; ++q) {
@@ -815,10 +852,11 @@ __global__ __launch_bounds__(T) void k_fused(const SimDev *__restrict__ sims, co
                             Yw[q] = rQp[o0][q][tw];
                             Yn[q] = rQp[on][q][tid];
                         }
-                        const double Ys[2] = {elo ? Y[0] : cin.qp0, elo ? Y[1] : cin.qp1};
+                        const PT Ys[2] = {elo ? Y[0] : cin.qp0, elo ? Y[1] : cin.qp1};
                         rhs_P(S, cin.g, cin.vx, cin.vy, Y, Ye, Yw, Yn, Ys, Rp);
-                        st32(Po, o, 0.5 * ((cin.p0 + Y[0]) + Rp[0]));
-                        st32(Po, N + o, 0.5 * ((cin.p1 + Y[1]) + Rp[1]));
+                        const unsigned oP = rm4 * nx * (unsigned)sizeof(PT), NP = N * (unsigned)sizeof(PT);
+                        buf_st(rPo, bP, oP, (PT)0.5 * ((cin.p0 + Y[0]) + Rp[0]));
+                        buf_st(rPo, bP, NP + oP, (PT)0.5 * ((cin.p1 + Y[1]) + Rp[1]));
                     }
                 }
                 cout.q0 = X[0];
@@ -880,6 +918,7 @@ __device__ __forceinline__ bool site_of(const SiteBlock *blk, const SimDev *sims
     return true;
 }
 
+template <typename PT>
 __global__ __launch_bounds__(256) void k_mp_sigE(const SimDev *__restrict__ sims, const SiteBlock *__restrict__ blk,
                                                  int cur, int *__restrict__ d_t) {
     if (d_t && blockIdx.x == 0 && threadIdx.x == 0) d_t[0] = d_t[0] + 1;
@@ -887,10 +926,10 @@ __global__ __launch_bounds__(256) void k_mp_sigE(const SimDev *__restrict__ sims
     if (!site_of(blk, sims, sim, x, y)) return;
     const SimDev &S = sims[sim];
     const size_t N = (size_t)S.nx * S.ny;
-    const double *P = S.P[cur];
+    const PT *P = static_cast<const PT *>(S.P[cur]);
     Nb q = nbrs(x, y, S.nx, S.ny, S.walls);
-    double Pc[2] = {P[q.c], P[N + q.c]}, Pe[2] = {P[q.e], P[N + q.e]}, Pw[2] = {P[q.w], P[N + q.w]};
-    double Pn[2] = {P[q.n], P[N + q.n]}, Ps[2] = {P[q.s], P[N + q.s]};
+    PT Pc[2] = {P[q.c], P[N + q.c]}, Pe[2] = {P[q.e], P[N + q.e]}, Pw[2] = {P[q.w], P[N + q.w]};
+    PT Pn[2] = {P[q.n], P[N + q.n]}, Ps[2] = {P[q.s], P[N + q.s]};
     float E[4];
     ericksen(S, Pc, Pe, Pw, Pn, Ps, E);
     for (int k = 0; k < 4; ++k) S.sE[k * N + q.c] = E[k];
@@ -969,8 +1008,9 @@ __device__ __forceinline__ void gather3(const float *f, size_t N, const Nb &q, f
         Xs[k] = f[k * N + q.s];
     }
 }
-__device__ __forceinline__ void gather2(const double *f, size_t N, const Nb &q, double X[2], double Xe[2], double Xw[2],
-                                        double Xn[2], double Xs[2]) {
+template <typename PT>
+__device__ __forceinline__ void gather2(const PT *f, size_t N, const Nb &q, PT X[2], PT Xe[2], PT Xw[2], PT Xn[2],
+                                        PT Xs[2]) {
     for (int k = 0; k < 2; ++k) {
         X[k] = f[k * N + q.c];
         Xe[k] = f[k * N + q.e];
@@ -980,6 +1020,7 @@ __device__ __forceinline__ void gather2(const double *f, size_t N, const Nb &q, 
     }
 }
 
+template <typename PT>
 __global__ __launch_bounds__(256) void k_mp_pred(const SimDev *__restrict__ sims, const SiteBlock *__restrict__ blk,
                                                  int cur) {
     int sim, x, y;
@@ -991,15 +1032,18 @@ __global__ __launch_bounds__(256) void k_mp_pred(const SimDev *__restrict__ sims
     float ux = S.v[q.c], uy = S.v[N + q.c];
     float X[3], Xe[3], Xw[3], Xn[3], Xs[3], Rs[3];
     gather3(S.sig[cur], N, q, X, Xe, Xw, Xn, Xs);
-    double Y[2], Ye[2], Yw[2], Yn[2], Ys[2], Rp[2];
-    gather2(S.P[cur], N, q, Y, Ye, Yw, Yn, Ys);
-    Stiff k = stiffness(S, reinterpret_cast<const float4 *>(S.tab), (float)Y[0], (float)Y[1]);
+    PT Y[2], Ye[2], Yw[2], Yn[2], Ys[2], Rp[2];
+    gather2(static_cast<const PT *>(S.P[cur]), N, q, Y, Ye, Yw, Yn, Ys);
+    Stiff k = stiffness(S, reinterpret_cast<const float4 *>(S.tab), (float)((PT)S.pref[0] + Y[0]),
+                        (float)((PT)S.pref[1] + Y[1]));
     rhs_sigma(S, k, g, ux, uy, X, Xe, Xw, Xn, Xs, Rs);
     rhs_P(S, g, ux, uy, Y, Ye, Yw, Yn, Ys, Rp);
     for (int c = 0; c < 3; ++c) S.sps[c * N + q.c] = X[c] + Rs[c];
-    for (int c = 0; c < 2; ++c) S.spp[c * N + q.c] = Y[c] + Rp[c];
+    PT *spp = static_cast<PT *>(S.spp);
+    for (int c = 0; c < 2; ++c) spp[c * N + q.c] = Y[c] + Rp[c];
 }
 
+template <typename PT>
 __global__ __launch_bounds__(256) void k_mp_corr(const SimDev *__restrict__ sims, const SiteBlock *__restrict__ blk,
                                                  int cur) {
     int sim, x, y;
@@ -1009,19 +1053,20 @@ __global__ __launch_bounds__(256) void k_mp_corr(const SimDev *__restrict__ sims
     Nb q = nbrs(x, y, S.nx, S.ny, S.walls);
     Grad g = grad_at(S, q);
     float ux = S.v[q.c], uy = S.v[N + q.c];
-    const double *P = S.P[cur];
-    Stiff k = stiffness(S, reinterpret_cast<const float4 *>(S.tab), (float)P[q.c], (float)P[N + q.c]);
+    const PT *P = static_cast<const PT *>(S.P[cur]);
+    Stiff k = stiffness(S, reinterpret_cast<const float4 *>(S.tab), (float)((PT)S.pref[0] + P[q.c]),
+                        (float)((PT)S.pref[1] + P[N + q.c]));
     float X[3], Xe[3], Xw[3], Xn[3], Xs[3], Rs[3];
     gather3(S.sps, N, q, X, Xe, Xw, Xn, Xs);
-    double Y[2], Ye[2], Yw[2], Yn[2], Ys[2], Rp[2];
-    gather2(S.spp, N, q, Y, Ye, Yw, Yn, Ys);
+    PT Y[2], Ye[2], Yw[2], Yn[2], Ys[2], Rp[2];
+    gather2(static_cast<const PT *>(S.spp), N, q, Y, Ye, Yw, Yn, Ys);
     rhs_sigma(S, k, g, ux, uy, X, Xe, Xw, Xn, Xs, Rs);
     rhs_P(S, g, ux, uy, Y, Ye, Yw, Yn, Ys, Rp);
     const float *sg = S.sig[cur];
     float *so = S.sig[cur ^ 1];
-    double *Po = S.P[cur ^ 1];
+    PT *Po = static_cast<PT *>(S.P[cur ^ 1]);
     for (int c = 0; c < 3; ++c) so[c * N + q.c] = 0.5f * ((sg[c * N + q.c] + X[c]) + Rs[c]);
-    for (int c = 0; c < 2; ++c) Po[c * N + q.c] = 0.5 * ((P[c * N + q.c] + Y[c]) + Rp[c]);
+    for (int c = 0; c < 2; ++c) Po[c * N + q.c] = (PT)0.5 * ((P[c * N + q.c] + Y[c]) + Rp[c]);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1043,16 +1088,17 @@ __global__ __launch_bounds__(256) void k_readout(const SimDev *__restrict__ sims
     pull_pops<HT>(S, reinterpret_cast<const HT *>(S.h[cur]), x, y, d);
     float drho, ux, uy;
     collide(d, Fx, Fy, S.omega, S.guo, drho, ux, uy);
+    typedef typename PolOf<HT>::T PT;
     const float *sg = S.sig[cur];
-    const double *P = S.P[cur];
+    const PT *P = static_cast<const PT *>(S.P[cur]);
     out[0 * N + q.c] = drho;
     out[1 * N + q.c] = ux;
     out[2 * N + q.c] = uy;
     out[3 * N + q.c] = sg[q.c];
     out[4 * N + q.c] = sg[N + q.c];
     out[5 * N + q.c] = sg[2 * N + q.c];
-    out[6 * N + q.c] = (float)P[q.c];
-    out[7 * N + q.c] = (float)P[N + q.c];
+    out[6 * N + q.c] = (float)((PT)S.pref[0] + P[q.c]);
+    out[7 * N + q.c] = (float)((PT)S.pref[1] + P[N + q.c]);
     out[8 * N + q.c] = fpx;
     out[9 * N + q.c] = fpy;
 }
@@ -1324,19 +1370,26 @@ int fused_blocks_per_cu(int T, bool fp16, bool walls, bool pol) {
 
 hipError_t launch_multipass(bool fp16, int nblocks, hipStream_t st, const SimDev *sims, const BodyDev *bodies,
                             const SiteBlock *blk, int cur, int *d_t) {
-    k_mp_sigE<<<nblocks, 256, 0, st>>>(sims, blk, cur, d_t);
-    if (fp16)
+    if (fp16) {
+        k_mp_sigE<float><<<nblocks, 256, 0, st>>>(sims, blk, cur, d_t);
         k_mp_lb<__half><<<nblocks, 256, 0, st>>>(sims, bodies, blk, cur);
-    else
+        k_mp_pred<float><<<nblocks, 256, 0, st>>>(sims, blk, cur);
+        k_mp_corr<float><<<nblocks, 256, 0, st>>>(sims, blk, cur);
+    } else {
+        k_mp_sigE<double><<<nblocks, 256, 0, st>>>(sims, blk, cur, d_t);
         k_mp_lb<float><<<nblocks, 256, 0, st>>>(sims, bodies, blk, cur);
-    k_mp_pred<<<nblocks, 256, 0, st>>>(sims, blk, cur);
-    k_mp_corr<<<nblocks, 256, 0, st>>>(sims, blk, cur);
+        k_mp_pred<double><<<nblocks, 256, 0, st>>>(sims, blk, cur);
+        k_mp_corr<double><<<nblocks, 256, 0, st>>>(sims, blk, cur);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_readout(bool fp16, int nblocks, int block0, hipStream_t st, const SimDev *sims, const BodyDev *bodies,
                           const SiteBlock *blk, int cur, float *out) {
-    k_mp_sigE<<<nblocks, 256, 0, st>>>(sims, blk + block0, cur, nullptr);
+    if (fp16)
+        k_mp_sigE<float><<<nblocks, 256, 0, st>>>(sims, blk + block0, cur, nullptr);
+    else
+        k_mp_sigE<double><<<nblocks, 256, 0, st>>>(sims, blk + block0, cur, nullptr);
     if (fp16)
         k_readout<__half><<<nblocks, 256, 0, st>>>(sims, bodies, blk + block0, cur, out);
     else
