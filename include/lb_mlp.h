@@ -62,6 +62,19 @@ int lb_mlp_train_step(lb_mlp *m, const float *X, const float *Y, int32_t batch, 
 
 int lb_mlp_destroy(lb_mlp *m);
 
+/* lb_mlp_forward for callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): no handle, no arena, and no device or host allocation
+ * in the call.  cfg: the network's widths (n_layers, widths; max_batch and the Adam fields are
+ * ignored); params: device FP32 parameters in the layout above; X (batch x w[0]) and Y
+ * (batch x w[L]): device FP32, row major.  The hidden activations live in a fixed scratch array of
+ * the library in each GPU's memory (2^20 floats, 4 MiB, held until the process ends; its address
+ * is looked up on the first call on a device): batch x (widest hidden layer) must not exceed
+ * 2^19 (LB_ERANGE otherwise).  Every call on one GPU uses that GPU's array, so calls that may
+ * overlap on one GPU (different streams, threads) race; calls in order on one stream are safe.
+ * Same products and results as lb_mlp_forward.  Asynchronous on hip_stream. */
+int lb_mlp_forward_noalloc(const lb_mlp_config *cfg, const float *params, const float *X, int32_t batch,
+                           float *Y, void *hip_stream);
+
 /* D = A B with BF16 operands and FP32 accumulation on the matrix cores (the product the network
  * uses), for testing: A (M x K), B (K x N), D (M x N), all row-major FP32 device arrays; the
  * operands are rounded to BF16 (nearest even).  Asynchronous on hip_stream. */

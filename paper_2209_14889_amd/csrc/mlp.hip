@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -279,6 +280,32 @@ hipError_t gemm(int epi, const float *A, long sam, long sak, const float *B, lon
     return hipGetLastError();
 }
 
+// ---- forward pass without allocation ------------------------------------------------------
+// The hidden activations of lb_mlp_forward_noalloc live in this file-scope device array, two
+// ping-pong halves of kScratchFloats / 2 floats.  Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in for the symbol): each device's copy is looked up once
+// with hipGetSymbolAddress and its address kept per device.
+constexpr size_t kScratchFloats = size_t(1) << 20;   // 4 MiB per GPU, held until the process ends
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) float scratch[kScratchFloats];
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_on_current_device(float **out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LB_EINVAL, "device index %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(LB_EDEVICE, "no device address for the scratch array");
+        g_scratch_ptr[dev] = static_cast<float *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return LB_OK;
+}
+
 // forward into the activation buffers; returns the output pointer (batch x w[L])
 int forward(lb_mlp *m, const float *X, int B) {
     const Layout &lo = m->lo;
@@ -431,6 +458,37 @@ int lb_mlp_train_step(lb_mlp *m, const float *X, const float *Y, int32_t batch, 
 int lb_mlp_destroy(lb_mlp *m) {
     if (!m) return fail(LB_EINVAL, "NULL argument");
     delete m;
+    return LB_OK;
+}
+
+int lb_mlp_forward_noalloc(const lb_mlp_config *cfg, const float *params, const float *X, int32_t batch, float *Y,
+                           void *hip_stream) {
+    if (!cfg || !params || !X || !Y) return fail(LB_EINVAL, "NULL argument");
+    const int L = cfg->n_layers;
+    if (L < 1 || L > 8) return fail(LB_EINVAL, "n_layers must be 1..8");
+    int wmax_hidden = 0;
+    for (int l = 0; l <= L; ++l) {
+        if (cfg->widths[l] < 1 || cfg->widths[l] > 4096) return fail(LB_EINVAL, "layer widths must be 1..4096");
+        if (l > 0 && l < L) wmax_hidden = std::max(wmax_hidden, cfg->widths[l]);
+    }
+    if (batch < 1) return fail(LB_ERANGE, "batch must be positive");
+    if ((size_t)batch * (size_t)wmax_hidden > kScratchFloats / 2)
+        return fail(LB_ERANGE, "batch %d x hidden width %d exceeds the scratch limit of %zu values", batch, wmax_hidden,
+                    kScratchFloats / 2);
+    float *buf = nullptr;
+    int rc = scratch_on_current_device(&buf);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const float *in = X;
+    size_t off = 0;   // parameter offset of W_l
+    for (int l = 0; l < L; ++l) {
+        const int K = cfg->widths[l], N = cfg->widths[l + 1];
+        const float *W = params + off, *b = params + off + (size_t)N * K;
+        off += (size_t)N * K + N;
+        float *out = l + 1 < L ? buf + (size_t)(l & 1) * (kScratchFloats / 2) : Y;
+        HIPCHK(gemm(l + 1 < L ? EPI_BIAS_TANH : EPI_BIAS, in, K, 1, W, 1, K, out, batch, N, K, b, nullptr, st));
+        in = out;
+    }
     return LB_OK;
 }
 

@@ -36,8 +36,10 @@ def lib():
         L.lb_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_float, vp]
         L.lb_mlp_destroy.argtypes = [vp]
         L.lb_mlp_gemm_bf16.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp]
+        L.lb_mlp_forward_noalloc.argtypes = [cfgp, vp, vp, ctypes.c_int32, vp, vp]
         for n in ("lb_mlp_query_bytes", "lb_mlp_n_params", "lb_mlp_create", "lb_mlp_set_params", "lb_mlp_get_params",
-                  "lb_mlp_forward", "lb_mlp_gradients", "lb_mlp_train_step", "lb_mlp_destroy", "lb_mlp_gemm_bf16"):
+                  "lb_mlp_forward", "lb_mlp_gradients", "lb_mlp_train_step", "lb_mlp_destroy", "lb_mlp_gemm_bf16",
+                  "lb_mlp_forward_noalloc"):
             getattr(L, n).restype = ctypes.c_int
         _ready = True
     return L
@@ -84,6 +86,16 @@ def gemm_bf16(A, B, stream=None):
     st = stream if stream is not None else torch.cuda.current_stream(A.device)
     _lb.check(lib().lb_mlp_gemm_bf16(_dev(A), _dev(B), _dev(D), M, N, K, ctypes.c_void_p(st.cuda_stream)))
     return D
+
+
+def forward_noalloc(widths, params, X, Y, stream=None) -> None:
+    """Y = network(X) through lb_mlp_forward_noalloc: params, X and Y are float32 cuda tensors the
+    caller owns (Y preallocated, batch x widths[-1]); nothing is allocated by the call."""
+    import torch
+    assert params.is_contiguous() and X.is_contiguous() and Y.is_contiguous()
+    st = stream if stream is not None else torch.cuda.current_stream(X.device)
+    _lb.check(lib().lb_mlp_forward_noalloc(ctypes.byref(make_config(widths, 1)), _dev(params), _dev(X), X.shape[0],
+                                           _dev(Y), ctypes.c_void_p(st.cuda_stream)))
 
 
 class MLP:
