@@ -940,11 +940,14 @@ static int create_impl(const lb_sim_params *sims, int n_sims, const lb_options *
         d.kappa = (float)p.kappa;
         d.Gamma = (float)p.Gamma;
         const double K1111 = p.Kx[0], K1122 = p.Kx[1], K2222 = p.Kx[2], K1212 = p.Kx[3];
-        d.cA = (float)(K1111 - 2 * K1122 - 4 * K1212 + K2222);
-        d.cB = (float)(K1111 - K2222);
-        d.S1 = (float)(3 * K1111 + 2 * K1122 + 4 * K1212 + 3 * K2222);
-        d.S2 = (float)(K1111 + 6 * K1122 - 4 * K1212 + K2222);
-        d.S3 = (float)(K1111 - 2 * K1122 + 4 * K1212 + K2222);
+        const double cA = K1111 - 2 * K1122 - 4 * K1212 + K2222, cB = K1111 - K2222;
+        d.cA8 = (float)(cA / 8);
+        d.cA2 = (float)(cA / 2);
+        d.cB2 = (float)(cB / 2);
+        d.s1 = (float)((3 * K1111 + 2 * K1122 + 4 * K1212 + 3 * K2222) / 8);
+        d.s2 = (float)((K1111 + 6 * K1122 - 4 * K1212 + K2222) / 8);
+        d.s3 = (float)((K1111 - 2 * K1122 + 4 * K1212 + K2222) / 4);
+        d.kap4 = (float)(0.25 * p.kappa);
         const Table &tb = *tabs[sp.tab];
         d.smax = (float)(p.P_clamp * p.P_clamp);
         d.inv_ds = (float)(kStiffSeg / (p.P_clamp * p.P_clamp));

@@ -27,9 +27,11 @@ struct SimDev {
     float omega, guo;               // 1/tau and 1 - 1/(2 tau)  (BGK, Guo forcing)
     float inv_eta, D;               // 1/eta_p, D_p
     float xi, alpha, beta, kappa, Gamma;
-    float cA, cB;                   // K1111-2K1122-4K1212+K2222, K1111-K2222
-    float S1, S2, S3;               // isotropic parts: 3K1111+2K1122+4K1212+3K2222,
-                                    // K1111+6K1122-4K1212+K2222, K1111-2K1122+4K1212+K2222
+    float cA8, cA2, cB2;            // cA / 8, cA / 2, cB / 2 with cA = K1111-2K1122-4K1212+K2222,
+                                    // cB = K1111-K2222 (the anisotropic parts of C~)
+    float s1, s2, s3;               // isotropic parts: (3K1111+2K1122+4K1212+3K2222) / 8,
+                                    // (K1111+6K1122-4K1212+K2222) / 8, (K1111-2K1122+4K1212+K2222) / 4
+    float kap4;                     // kappa / 4 (the Ericksen gradient term from half-differences)
     float smax, inv_ds;             // table range P_clamp^2 and intervals per unit s
     float A2max, A4max;             // a2/s and a4/s^2 at smax
     float inv_scale, scale;         // FP16 storage scale 2^-S and 2^S (1 for FP32)

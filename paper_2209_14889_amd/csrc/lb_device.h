@@ -5,6 +5,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
+#include <type_traits>
 
 #include "lb_common.h"
 
@@ -175,9 +176,14 @@ __device__ __forceinline__ void collide(float d[9], float Fx, float Fy, float om
 
 // ---- stiffness C~(P) (App. B) via piecewise cubics of a2/s and a4/s^2 in s = |P|^2 ---------
 // a2 cos(2 th) = A2 (Px^2 - Py^2), a2 sin(2 th) = A2 2 Px Py, and the same for a4 with the
-// squares of those harmonics, so no angle and no division by |P| are needed.
+// squares of those harmonics, so no angle and no division by |P| are needed.  The operator on
+// plain components (Xxx, Xyy, Xxy) is
+//   C11 = (S1 + X1 + 4 X2) / 8, C22 = C11 - X2, C12 = (S2 - X1) / 8, C33 = (S3 - X1) / 4,
+//   C13 = (Y1 + 2 Y2) / 4, C23 = (2 Y2 - Y1) / 4,   C31 = C13 / 2, C32 = C23 / 2,
+// with X1 = a4 cos 4th cA, X2 = a2 cos 2th cB, Y1 = a4 sin 4th cA, Y2 = a2 sin 2th cB; Stiff
+// holds them pre-scaled: p = X1 / 8, q = X2 / 2, r = Y1 / 4, w = Y2 / 2.
 struct Stiff {
-    float X1, X2, Y1, Y2;   // a4 c4 cA, a2 c2 cB, a4 s4 cA, a2 s2 cB
+    float p, q, r, w;
 };
 
 // tab: kStiffSeg segments x two float4 (cubic coefficients c0..c3 of A2, then of A4), in LDS or
@@ -201,48 +207,49 @@ __device__ __forceinline__ Stiff stiffness(const SimDev &S, Tab tab, float Px, f
     }
     float dd = sx - sy, ee = 2.0f * Px * Py;
     Stiff k;
-    k.X1 = A4 * (dd * dd - ee * ee) * S.cA;
-    k.Y1 = A4 * (2.0f * dd * ee) * S.cA;
-    k.X2 = A2 * dd * S.cB;
-    k.Y2 = A2 * ee * S.cB;
+    k.p = A4 * (dd * dd - ee * ee) * S.cA8;
+    k.r = A4 * (dd * ee) * S.cA2;
+    k.q = A2 * dd * S.cB2;
+    k.w = A2 * ee * S.cB2;
     return k;
 }
 
 // y = C~ x on plain components (xx, yy, xy)
 __device__ __forceinline__ void stiff_apply(const SimDev &S, const Stiff &k, float a, float b, float c,
                                             float &o0, float &o1, float &o2) {
-    float C11 = 0.125f * (k.X1 + S.S1 + 4.0f * k.X2);
-    float C22 = C11 - k.X2;
-    float C12 = 0.125f * (S.S2 - k.X1);
-    float C33 = 0.25f * (S.S3 - k.X1);
-    float C13 = 0.25f * (k.Y1 + 2.0f * k.Y2);
-    float C23 = 0.25f * (2.0f * k.Y2 - k.Y1);
+    float C11 = (S.s1 + k.p) + k.q;
+    float C22 = fmaf(-2.0f, k.q, C11);
+    float C12 = S.s2 - k.p;
+    float C33 = fmaf(-2.0f, k.p, S.s3);
+    float C13 = k.r + k.w;
+    float C23 = k.w - k.r;
     o0 = C11 * a + C12 * b + C13 * c;
     o1 = C12 * a + C22 * b + C23 * c;
     o2 = 0.5f * (C13 * a + C23 * b) + C33 * c;
 }
 
-// velocity gradient pieces at a site from central differences
+// velocity gradient pieces at a site from central differences of HALF the velocity (h = v / 2 at
+// the four neighbours), so the differences need no halving
 struct Grad {
     float psi0, psi1, psi2, om;   // Psi_xx, Psi_yy, Psi_xy, Omega_xy
 };
 
-__device__ __forceinline__ Grad grad_v(float vxe, float vxw, float vxn, float vxs,
-                                       float vye, float vyw, float vyn, float vys) {
-    float Gxx = 0.5f * (vxe - vxw), Gxy = 0.5f * (vye - vyw);
-    float Gyx = 0.5f * (vxn - vxs), Gyy = 0.5f * (vyn - vys);
+__device__ __forceinline__ Grad grad_v(float hxe, float hxw, float hxn, float hxs,
+                                       float hye, float hyw, float hyn, float hys) {
+    const float gxy = hye - hyw, gyx = hxn - hxs;   // d_x v_y, d_y v_x
     Grad g;
-    g.psi0 = Gxx;
-    g.psi1 = Gyy;
-    g.psi2 = 0.5f * (Gxy + Gyx);
-    g.om = 0.5f * (Gxy - Gyx);
+    g.psi0 = hxe - hxw;
+    g.psi1 = hyn - hys;
+    g.psi2 = 0.5f * (gxy + gyx);
+    g.om = 0.5f * (gxy - gyx);
     return g;
 }
 
 // right-hand side of eqStiffCons (corotational derivative) for one component set:
 // -(v.grad)X - (Omega X - X Omega) + C~(Psi - X/eta_p) + D_p lap X.
 // X[c] centre, e/w/n/s neighbours of each component.
-__device__ __forceinline__ void rhs_sigma(const SimDev &S, const Stiff &k, const Grad &g, float ux, float uy,
+// hx, hy: half the velocity, so the central differences need no halving.
+__device__ __forceinline__ void rhs_sigma(const SimDev &S, const Stiff &k, const Grad &g, float hx, float hy,
                                           const float X[3], const float Xe[3], const float Xw[3],
                                           const float Xn[3], const float Xs[3], float R[3]) {
     float a = g.psi0 - S.inv_eta * X[0];
@@ -256,7 +263,7 @@ __device__ __forceinline__ void rhs_sigma(const SimDev &S, const Stiff &k, const
     float Jv[3] = {J0, -J0, J2};
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        float adv = ux * (0.5f * (Xe[q] - Xw[q])) + uy * (0.5f * (Xn[q] - Xs[q]));
+        float adv = hx * (Xe[q] - Xw[q]) + hy * (Xn[q] - Xs[q]);
         float lap = ((Xe[q] + Xw[q]) + (Xn[q] + Xs[q])) - 4.0f * X[q];
         R[q] = Cv[q] - Jv[q] - adv + S.D * lap;
     }
@@ -275,8 +282,10 @@ template <> struct PolOf<__half> { typedef float T; };
 
 // Local quantities of eqBE and the Ericksen stress from the stored values.  The slope
 // a = alpha + beta |P|^2 cancels to near zero at the equilibrium magnitude, so it is formed in FP64
-// from the exact value pref + Y; the neighbour differences are formed in the storage precision
-// (exact for FP64, exact for FP32 offsets of close neighbours) and the rest in FP32.
+// from the exact value pref + Y (formed in FP32 from the rounded centre value it feeds a noise
+// into the molecular field that moves a 1000-step FP16 run by several 1e-3); the neighbour
+// differences are formed in the storage precision (exact for FP64, exact for FP32 offsets of
+// close neighbours) and the rest in FP32.
 struct PLocal {
     float c[2];      // centre P = pref + Y
     float d[4][2];   // e, w, n, s minus the centre
@@ -302,15 +311,15 @@ __device__ __forceinline__ PLocal p_local(const SimDev &S, const PT Y[2], const 
 // right-hand side of eqBE for the stored offsets: -(v.grad)Y - Omega P + xi Psi P - Gamma h(P),
 // h = (alpha + beta |P|^2) P - kappa lap P (pref is constant, so the gradients of P are those of Y)
 template <typename PT>
-__device__ __forceinline__ void rhs_P(const SimDev &S, const Grad &g, float ux, float uy, const PT Y[2],
+__device__ __forceinline__ void rhs_P(const SimDev &S, const Grad &g, float hx, float hy, const PT Y[2],
                                       const PT Ye[2], const PT Yw[2], const PT Yn[2], const PT Ys[2], PT R[2]) {
     const PLocal L = p_local(S, Y, Ye, Yw, Yn, Ys);
     const float lap0 = (L.d[0][0] + L.d[1][0]) + (L.d[2][0] + L.d[3][0]);
     const float lap1 = (L.d[0][1] + L.d[1][1]) + (L.d[2][1] + L.d[3][1]);
     const float h0 = L.a * L.c[0] - S.kappa * lap0;
     const float h1 = L.a * L.c[1] - S.kappa * lap1;
-    const float adv0 = ux * (0.5f * (L.d[0][0] - L.d[1][0])) + uy * (0.5f * (L.d[2][0] - L.d[3][0]));
-    const float adv1 = ux * (0.5f * (L.d[0][1] - L.d[1][1])) + uy * (0.5f * (L.d[2][1] - L.d[3][1]));
+    const float adv0 = hx * (L.d[0][0] - L.d[1][0]) + hy * (L.d[2][0] - L.d[3][0]);
+    const float adv1 = hx * (L.d[0][1] - L.d[1][1]) + hy * (L.d[2][1] - L.d[3][1]);
     R[0] = (PT)(-adv0 - g.om * L.c[1] + S.xi * (g.psi0 * L.c[0] + g.psi2 * L.c[1]) - S.Gamma * h0);
     R[1] = (PT)(-adv1 + g.om * L.c[0] + S.xi * (g.psi2 * L.c[0] + g.psi1 * L.c[1]) - S.Gamma * h1);
 }
@@ -326,15 +335,16 @@ __device__ __forceinline__ void ericksen(const SimDev &S, const PT P[2], const P
     const float lap1 = (L.d[0][1] + L.d[1][1]) + (L.d[2][1] + L.d[3][1]);
     const float hx = L.a * P0 - kap * lap0;
     const float hy = L.a * P1 - kap * lap1;
-    const float dxPx = 0.5f * (L.d[0][0] - L.d[1][0]), dyPx = 0.5f * (L.d[2][0] - L.d[3][0]);
-    const float dxPy = 0.5f * (L.d[0][1] - L.d[1][1]), dyPy = 0.5f * (L.d[2][1] - L.d[3][1]);
+    // twice the central differences; kappa / 4 takes the halves
+    const float dxPx = L.d[0][0] - L.d[1][0], dyPx = L.d[2][0] - L.d[3][0];
+    const float dxPy = L.d[0][1] - L.d[1][1], dyPy = L.d[2][1] - L.d[3][1];
     const float anti = -0.5f * (P0 * hy - hx * P1);
     const float sym = 0.5f * xi * (P0 * hy + hx * P1);
-    const float gxy = kap * (dxPx * dyPx + dxPy * dyPy);
-    E[0] = xi * P0 * hx - kap * (dxPx * dxPx + dxPy * dxPy);
+    const float gxy = S.kap4 * (dxPx * dyPx + dxPy * dyPy);
+    E[0] = xi * P0 * hx - S.kap4 * (dxPx * dxPx + dxPy * dxPy);
     E[1] = anti + sym - gxy;
     E[2] = -anti + sym - gxy;
-    E[3] = xi * P1 * hy - kap * (dyPx * dyPx + dyPy * dyPy);
+    E[3] = xi * P1 * hy - S.kap4 * (dyPx * dyPx + dyPy * dyPy);
 }
 
 // (x - o) mod n for |x - o| < 2n, without an integer division

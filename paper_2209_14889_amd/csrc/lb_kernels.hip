@@ -523,7 +523,7 @@ __global__ __launch_bounds__(T, (WALLS || !std::is_same<HT, __half>::value) ? 3 
     __shared__ PT rP[4][2][TP];       // polarization, rows f-3 .. f
     __shared__ float rS[3][3][T];     // stress rows f-3 .. f-1
     __shared__ float rE[2][2][TP];    // Ericksen xx and yx, rows f-2 .. f-1
-    __shared__ float rV[2][2][T];     // velocity rows f-3 .. f-2
+    __shared__ float rV[2][2][T];     // half-velocity rows f-3 .. f-2
     __shared__ float rQs[2][3][T];    // predicted stress rows f-4 .. f-3
     __shared__ PT rQp[2][2][TP];      // predicted polarization, rows f-4 .. f-3
     __shared__ float4 sTab[2 * kStiffSeg];     // stiffness cubics of the item's simulation
@@ -621,7 +621,7 @@ __global__ __launch_bounds__(T, (WALLS || !std::is_same<HT, __half>::value) ? 3 
         // (the corrector's frozen inputs and the next predictor's south neighbours) and stage E's
         // predicted centre (the next corrector's south neighbour).
         struct Carry {
-            float vx, vy, s0, s1, s2;
+            float hx, hy, s0, s1, s2;      // hx, hy: half the velocity
             PT p0, p1;
             Grad g;
             Stiff k;
@@ -756,8 +756,8 @@ __global__ __launch_bounds__(T, (WALLS || !std::is_same<HT, __half>::value) ? 3 
                     ib_force(S, bodies, cur, (int)x, (int)rm2, Fx, Fy);
                 float drho, ux, uy;
                 collide_t<Pop<HT>::kScaled>(d, Fx, Fy, S.omega, S.guo, sc, is, drho, ux, uy);
-                rV[o0][0][tid] = ux;
-                rV[o0][1][tid] = uy;
+                rV[o0][0][tid] = 0.5f * ux;   // the gradient and advection stages take v / 2
+                rV[o0][1][tid] = 0.5f * uy;
                 const int r = wi.y0 + j - 6;   // = f - 2
                 if (colE && r >= wi.y0 && r < wi.y0 + wi.l) {
                     const unsigned o = rm2 * nx * HB, NH = N * HB;
@@ -772,8 +772,8 @@ __global__ __launch_bounds__(T, (WALLS || !std::is_same<HT, __half>::value) ? 3 
 
             // ---- stage D: predictor at row f-3 (from j = 5 only the carried centre values)
             if (j >= 5 && colD) {
-                cout.vx = rV[o1][0][tid];
-                cout.vy = rV[o1][1][tid];
+                cout.hx = rV[o1][0][tid];
+                cout.hy = rV[o1][1][tid];
                 PT Pc[2] = {POL ? rP[a3][0][tid] : (PT)0, POL ? rP[a3][1][tid] : (PT)0};
                 float X[3];
 #pragma unroll
@@ -781,8 +781,8 @@ __global__ __launch_bounds__(T, (WALLS || !std::is_same<HT, __half>::value) ? 3 
                 if (j >= 6) {
                     // walls: mirror ghosts for sigma and P, no-slip (negated) ghosts for v
                     const bool dlo = walls && rm3 == 0u, dhi = walls && rm3 == ytop;
-                    const float vxn = dhi ? -cout.vx : rV[o0][0][tid], vyn = dhi ? -cout.vy : rV[o0][1][tid];
-                    const float vxs = dlo ? -cout.vx : cin.vx, vys = dlo ? -cout.vy : cin.vy;
+                    const float vxn = dhi ? -cout.hx : rV[o0][0][tid], vyn = dhi ? -cout.hy : rV[o0][1][tid];
+                    const float vxs = dlo ? -cout.hx : cin.hx, vys = dlo ? -cout.hy : cin.hy;
                     const float sxe = xe ? -1.0f : 1.0f, sxw = xw ? -1.0f : 1.0f;   // no-slip ghosts
                     cout.g = grad_v(sxe * rV[o1][0][te], sxw * rV[o1][0][tw], vxn, vxs,
                                     sxe * rV[o1][1][te], sxw * rV[o1][1][tw], vyn, vys);
@@ -798,7 +798,7 @@ __global__ __launch_bounds__(T, (WALLS || !std::is_same<HT, __half>::value) ? 3 
                         Xn[q] = rS[bn][q][tid];
                     }
                     const float Xs[3] = {dlo ? X[0] : cin.s0, dlo ? X[1] : cin.s1, dlo ? X[2] : cin.s2};
-                    rhs_sigma(S, cout.k, cout.g, cout.vx, cout.vy, X, Xe, Xw, Xn, Xs, Rs);
+                    rhs_sigma(S, cout.k, cout.g, cout.hx, cout.hy, X, Xe, Xw, Xn, Xs, Rs);
                     rQs[o1][0][tid] = X[0] + Rs[0];
                     rQs[o1][1][tid] = X[1] + Rs[1];
                     rQs[o1][2][tid] = X[2] + Rs[2];
@@ -809,7 +809,7 @@ __global__ __launch_bounds__(T, (WALLS || !std::is_same<HT, __half>::value) ? 3 
                         PT Pn[2] = {rP[an][0][tid], rP[an][1][tid]};
                         PT Ps[2] = {dlo ? Pc[0] : cin.p0, dlo ? Pc[1] : cin.p1};
                         PT Rp[2];
-                        rhs_P(S, cout.g, cout.vx, cout.vy, Pc, Pe, Pw, Pn, Ps, Rp);
+                        rhs_P(S, cout.g, cout.hx, cout.hy, Pc, Pe, Pw, Pn, Ps, Rp);
                         rQp[o1][0][tid] = Pc[0] + Rp[0];
                         rQp[o1][1][tid] = Pc[1] + Rp[1];
                     }
@@ -840,7 +840,7 @@ __global__ __launch_bounds__(T, (WALLS || !std::is_same<HT, __half>::value) ? 3 
                         Xn[q] = rQs[on][q][tid];
                     }
                     const float Xs[3] = {elo ? X[0] : cin.q0, elo ? X[1] : cin.q1, elo ? X[2] : cin.q2};
-                    rhs_sigma(S, cin.k, cin.g, cin.vx, cin.vy, X, Xe, Xw, Xn, Xs, Rs);
+                    rhs_sigma(S, cin.k, cin.g, cin.hx, cin.hy, X, Xe, Xw, Xn, Xs, Rs);
                     const unsigned o = rm4 * nx * 4u, N4 = N * 4u;
                     buf_stf(rSo, b4, o, 0.5f * ((cin.s0 + X[0]) + Rs[0]));
                     buf_stf(rSo, b4, N4 + o, 0.5f * ((cin.s1 + X[1]) + Rs[1]));
@@ -853,7 +853,7 @@ __global__ __launch_bounds__(T, (WALLS || !std::is_same<HT, __half>::value) ? 3 
                             Yn[q] = rQp[on][q][tid];
                         }
                         const PT Ys[2] = {elo ? Y[0] : cin.qp0, elo ? Y[1] : cin.qp1};
-                        rhs_P(S, cin.g, cin.vx, cin.vy, Y, Ye, Yw, Yn, Ys, Rp);
+                        rhs_P(S, cin.g, cin.hx, cin.hy, Y, Ye, Yw, Yn, Ys, Rp);
                         const unsigned oP = rm4 * nx * (unsigned)sizeof(PT), NP = N * (unsigned)sizeof(PT);
                         buf_st(rPo, bP, oP, (PT)0.5 * ((cin.p0 + Y[0]) + Rp[0]));
                         buf_st(rPo, bP, NP + oP, (PT)0.5 * ((cin.p1 + Y[1]) + Rp[1]));
@@ -993,7 +993,8 @@ __device__ __forceinline__ Grad grad_at(const SimDev &S, const Nb &q) {
     const size_t N = (size_t)S.nx * S.ny;
     const float *v = S.v;
     // no-slip ghosts beyond a wall: the negated velocity of the wall row
-    const float sn = q.hi ? -1.0f : 1.0f, ss = q.lo ? -1.0f : 1.0f, se = q.ri ? -1.0f : 1.0f, sw = q.le ? -1.0f : 1.0f;
+    // (and half of it: grad_v takes v / 2)
+    const float sn = q.hi ? -0.5f : 0.5f, ss = q.lo ? -0.5f : 0.5f, se = q.ri ? -0.5f : 0.5f, sw = q.le ? -0.5f : 0.5f;
     return grad_v(se * v[q.e], sw * v[q.w], sn * v[q.n], ss * v[q.s], se * v[N + q.e], sw * v[N + q.w], sn * v[N + q.n],
                   ss * v[N + q.s]);
 }
@@ -1029,15 +1030,15 @@ __global__ __launch_bounds__(256) void k_mp_pred(const SimDev *__restrict__ sims
     const size_t N = (size_t)S.nx * S.ny;
     Nb q = nbrs(x, y, S.nx, S.ny, S.walls);
     Grad g = grad_at(S, q);
-    float ux = S.v[q.c], uy = S.v[N + q.c];
+    float hx = 0.5f * S.v[q.c], hy = 0.5f * S.v[N + q.c];
     float X[3], Xe[3], Xw[3], Xn[3], Xs[3], Rs[3];
     gather3(S.sig[cur], N, q, X, Xe, Xw, Xn, Xs);
     PT Y[2], Ye[2], Yw[2], Yn[2], Ys[2], Rp[2];
     gather2(static_cast<const PT *>(S.P[cur]), N, q, Y, Ye, Yw, Yn, Ys);
     Stiff k = stiffness(S, reinterpret_cast<const float4 *>(S.tab), (float)((PT)S.pref[0] + Y[0]),
                         (float)((PT)S.pref[1] + Y[1]));
-    rhs_sigma(S, k, g, ux, uy, X, Xe, Xw, Xn, Xs, Rs);
-    rhs_P(S, g, ux, uy, Y, Ye, Yw, Yn, Ys, Rp);
+    rhs_sigma(S, k, g, hx, hy, X, Xe, Xw, Xn, Xs, Rs);
+    rhs_P(S, g, hx, hy, Y, Ye, Yw, Yn, Ys, Rp);
     for (int c = 0; c < 3; ++c) S.sps[c * N + q.c] = X[c] + Rs[c];
     PT *spp = static_cast<PT *>(S.spp);
     for (int c = 0; c < 2; ++c) spp[c * N + q.c] = Y[c] + Rp[c];
@@ -1052,7 +1053,7 @@ __global__ __launch_bounds__(256) void k_mp_corr(const SimDev *__restrict__ sims
     const size_t N = (size_t)S.nx * S.ny;
     Nb q = nbrs(x, y, S.nx, S.ny, S.walls);
     Grad g = grad_at(S, q);
-    float ux = S.v[q.c], uy = S.v[N + q.c];
+    float hx = 0.5f * S.v[q.c], hy = 0.5f * S.v[N + q.c];
     const PT *P = static_cast<const PT *>(S.P[cur]);
     Stiff k = stiffness(S, reinterpret_cast<const float4 *>(S.tab), (float)((PT)S.pref[0] + P[q.c]),
                         (float)((PT)S.pref[1] + P[N + q.c]));
@@ -1060,8 +1061,8 @@ __global__ __launch_bounds__(256) void k_mp_corr(const SimDev *__restrict__ sims
     gather3(S.sps, N, q, X, Xe, Xw, Xn, Xs);
     PT Y[2], Ye[2], Yw[2], Yn[2], Ys[2], Rp[2];
     gather2(static_cast<const PT *>(S.spp), N, q, Y, Ye, Yw, Yn, Ys);
-    rhs_sigma(S, k, g, ux, uy, X, Xe, Xw, Xn, Xs, Rs);
-    rhs_P(S, g, ux, uy, Y, Ye, Yw, Yn, Ys, Rp);
+    rhs_sigma(S, k, g, hx, hy, X, Xe, Xw, Xn, Xs, Rs);
+    rhs_P(S, g, hx, hy, Y, Ye, Yw, Yn, Ys, Rp);
     const float *sg = S.sig[cur];
     float *so = S.sig[cur ^ 1];
     PT *Po = static_cast<PT *>(S.P[cur ^ 1]);
