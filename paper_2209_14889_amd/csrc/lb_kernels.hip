@@ -873,8 +873,18 @@ __global__ __launch_bounds__(T, (WALLS || !std::is_same<HT, __half>::value) ? 3 
             inc_row(rm4, ny);
         };
 
-        // two iterations per trip with the register sets swapped, so no values are copied
+        // two iterations per trip with the register sets swapped, so no values are copied.  The
+        // waves' issue priority falls in thirds as the item progresses: a compute unit's SIMDs are
+        // shared by several work-groups, and under the hardware's oldest-first arbitration the
+        // last-dispatched ones would otherwise trail alone, at low VALU use, at the end.
+        const int q1 = niter / 3, q2 = (2 * niter) / 3;
         for (int j = 0; j < niter; j += 2) {
+            if (j >= q2)
+                __builtin_amdgcn_s_setprio(0);
+            else if (j >= q1)
+                __builtin_amdgcn_s_setprio(1);
+            else
+                __builtin_amdgcn_s_setprio(2);
             iterate(j, preA, preB, carA, carB);
             if (j + 1 < niter) iterate(j + 1, preB, preA, carB, carA);
         }
