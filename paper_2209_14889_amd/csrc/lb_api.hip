@@ -704,11 +704,13 @@ int choose_fused_config(lb_handle *h) {
     int dev = 0, cus = 256;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    // work-group width: lattices no wider than 64 or 128 run as full-width strips of that many
+    // lanes (no halo lanes and no idle waves); wider ones as 248-column strips of 256 lanes
     auto model_T = [&]() {
         if (h->opt.threads) return h->opt.threads;
         int mx = 0;
         for (const auto &sp : h->plan.sims) mx = std::max(mx, sp.nx);
-        return mx <= 120 ? 128 : 256;
+        return mx <= 64 ? 64 : mx <= 128 ? 128 : 256;
     };
     if (!h->opt.autotune) {
         int T = model_T();
