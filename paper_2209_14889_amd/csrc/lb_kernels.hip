@@ -357,10 +357,11 @@ __global__ __launch_bounds__(256) void k_ib_spread(const BodyDev *__restrict__ b
 // its patch).  Every block of a body repeats the node update (a few hundred nodes):
 //  ADVANCE: move the nodes from R(t) to R(t+1) by Heun with the velocity patch written during
 //  step t (App. A: overdamped, no slip); otherwise take R[cur] as it is;
-//  the patch origin for the new positions (3 sites of margin around the nodes);
-//  the forces of the nodes whose 4x4 footprint reaches the tile, at the new positions with the
-//  pull at time *d_t, gathered onto the tile's sites in node order (deterministic):
-//  f_IB(r) = sum_a f_a phi phi (App. A).
+//  the patch origin for the new positions (3 sites of margin around the nodes), found in the same
+//  pass as the centre of mass;
+//  every node's force at the new positions with the pull at time *d_t (once, each by the thread
+//  that lists the node), and of those the nodes whose 4x4 footprint reaches the tile gathered onto
+//  the tile's sites in node order (deterministic): f_IB(r) = sum_a f_a phi phi (App. A).
 // Tile 0 of each body publishes the new positions, all node forces and the origin; the other
 // blocks only read the current-parity buffers, so blocks never wait on each other.
 template <bool ADVANCE>
@@ -372,6 +373,7 @@ __global__ __launch_bounds__(256) void k_ib_step(const SimDev *__restrict__ sims
     __shared__ int2 sI[kMaxCand];
     __shared__ float4 sW[kMaxCand][2];
     __shared__ double2 sF[kMaxCand];
+    __shared__ double2 sFall[kMaxNodes];   // every node's force (each thread's own nodes)
     __shared__ int sCnt[4];
     __shared__ double sC[4][2];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -391,7 +393,8 @@ __global__ __launch_bounds__(256) void k_ib_step(const SimDev *__restrict__ sims
         ox = B.origin[4 * cur];
         oy = B.origin[4 * cur + 1];
     }
-    double mnx = 1e300, mny = 1e300, mxx = -1e300, mxy = -1e300;
+    // one pass for the extent and the centre of mass (the sums in block_com's order)
+    double mnx = 1e300, mny = 1e300, mxx = -1e300, mxy = -1e300, cx = 0.0, cy = 0.0;
     for (int a = tid; a < n; a += 256) {
         double2 R = Rc[a];
         if (ADVANCE) {
@@ -406,18 +409,26 @@ __global__ __launch_bounds__(256) void k_ib_step(const SimDev *__restrict__ sims
         mny = fmin(mny, R.y);
         mxx = fmax(mxx, R.x);
         mxy = fmax(mxy, R.y);
+        cx += R.x;
+        cy += R.y;
     }
     mnx = wave_min(mnx);
     mny = wave_min(mny);
     mxx = wave_max(mxx);
     mxy = wave_max(mxy);
+    cx = wave_sum(cx);
+    cy = wave_sum(cy);
     if (lane == 0) {
         sRed[wv][0] = mnx;
         sRed[wv][1] = mny;
         sRed[wv][2] = mxx;
         sRed[wv][3] = mxy;
+        sC[wv][0] = cx;
+        sC[wv][1] = cy;
     }
     __syncthreads();
+    const double2 com = make_double2(((sC[0][0] + sC[1][0]) + (sC[2][0] + sC[3][0])) / n,
+                                     ((sC[0][1] + sC[1][1]) + (sC[2][1] + sC[3][1])) / n);
     mnx = fmin(fmin(sRed[0][0], sRed[1][0]), fmin(sRed[2][0], sRed[3][0]));
     mny = fmin(fmin(sRed[0][1], sRed[1][1]), fmin(sRed[2][1], sRed[3][1]));
     mxx = fmax(fmax(sRed[0][2], sRed[1][2]), fmax(sRed[2][2], sRed[3][2]));
@@ -428,12 +439,14 @@ __global__ __launch_bounds__(256) void k_ib_step(const SimDev *__restrict__ sims
     if ((int)floor(mxx) + 3 - nox >= B.ps || (int)floor(mxy) + 3 - noy >= B.ps) bad = true;
 
     const double pf = pull_factor(B, (double)d_t[0]);
-    const double2 trap = trap_share(B, (double)d_t[0], block_com(sR, n, sC));
+    const double2 trap = trap_share(B, (double)d_t[0], com);
+    // every node's force once, by the thread that lists the node below (so no barrier)
+    for (int a = tid; a < n; a += 256) sFall[a] = node_force(B, sR, a, pf, trap);
     if (lead) {
         double2 *Fn = reinterpret_cast<double2 *>(B.fnode);
         double2 *Rd = reinterpret_cast<double2 *>(B.R[dst]);
         for (int a = tid; a < n; a += 256) {
-            Fn[a] = node_force(B, sR, a, pf, trap);
+            Fn[a] = sFall[a];
             if (ADVANCE) Rd[a] = sR[a];
         }
         if (tid == 0) {
@@ -473,7 +486,7 @@ __global__ __launch_bounds__(256) void k_ib_step(const SimDev *__restrict__ sims
                 sI[q] = make_int2(ix - X0, iy - Y0);
                 sW[q][0] = make_float4(wx[0], wx[1], wx[2], wx[3]);
                 sW[q][1] = make_float4(wy[0], wy[1], wy[2], wy[3]);
-                sF[q] = node_force(B, sR, a, pf, trap);
+                sF[q] = sFall[a];
             } else {
                 overflow = true;
             }
