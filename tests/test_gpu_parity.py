@@ -273,6 +273,29 @@ def test_launch_shapes_agree_bitwise():
     compare(g, r)
 
 
+def test_full_width_strips_agree_bitwise_and_the_model_uses_them():
+    """A lattice no wider than the work-group runs as one full-width strip (a lane's east and west
+    neighbours wrap within the strip, no halo lanes); any work-group at least that wide gives the
+    same bits, lanes beyond the lattice idle.  Without autotuning the launch model picks the
+    narrowest such work-group: 64 lanes up to 64 columns, 128 up to 128, else 256-lane strips."""
+    w = wl.small_case(46, 64, 40, n_bodies=1, radius=5.0, pull=2e-4)
+    say("case full-width strips 64x40 seed=46 one body, 120 steps, threads 64/128/256")
+    out = []
+    for T in (64, 128, 256):
+        g = lb.Sim(w, lb.make_options(fused_threads=T, seg_rows=7))
+        g.step(120)
+        out.append((g.fields(), g.nodes()))
+        g.close()
+    for f, n in out[1:]:
+        for k in lb.FIELDS:
+            assert np.array_equal(f[k], out[0][0][k]), k
+        assert np.array_equal(n[0], out[0][1][0])
+    for nx, T in ((64, 64), (100, 128), (128, 128), (129, 256)):
+        g = lb.Sim(wl.small_case(47, nx, 24, n_bodies=0), lb.make_options())
+        assert g.launch_shape()["threads"] == T, (nx, g.launch_shape())
+        g.close()
+
+
 @pytest.mark.parametrize("nx,ny", [(8, 8), (8, 13), (11, 8)])
 def test_smallest_lattices(nx, ny):
     """The smallest lattices the library accepts (8 x 8): narrower than one strip of any work-group
