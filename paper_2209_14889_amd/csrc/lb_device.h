@@ -180,8 +180,9 @@ __device__ __forceinline__ void collide(float d[9], float Fx, float Fy, float om
 // plain components (Xxx, Xyy, Xxy) is
 //   C11 = (S1 + X1 + 4 X2) / 8, C22 = C11 - X2, C12 = (S2 - X1) / 8, C33 = (S3 - X1) / 4,
 //   C13 = (Y1 + 2 Y2) / 4, C23 = (2 Y2 - Y1) / 4,   C31 = C13 / 2, C32 = C23 / 2,
-// with X1 = a4 cos 4th cA, X2 = a2 cos 2th cB, Y1 = a4 sin 4th cA, Y2 = a2 sin 2th cB; Stiff
-// holds them pre-scaled: p = X1 / 8, q = X2 / 2, r = Y1 / 4, w = Y2 / 2.
+// with X1 = a4 cos 4th cA, X2 = a2 cos 2th cB, Y1 = a4 sin 4th cA, Y2 = a2 sin 2th cB and the
+// isotropic parts S1, S2, S3 (SimDev holds S1 / 8, S2 / 8, S3 / 4); Stiff holds the angular ones
+// pre-scaled: p = X1 / 8, q = X2 / 2, r = Y1 / 4, w = Y2 / 2.
 struct Stiff {
     float p, q, r, w;
 };
