@@ -29,6 +29,11 @@ if ROOT not in sys.path:
 
 METRIC = "MLUPS and % HBM roofline per coupled step; surrogate-vs-LB speedup at 2% error"
 HBM_PEAK_GBS = 8000.0
+# MI355X vector peaks from its unit counts: 256 compute units x 4 SIMDs at 2.4 GHz; one wave64 VALU
+# instruction per SIMD every 4 cycles (614.4 G wave instructions/s); FP32 157.3 TFLOP/s with
+# packed FP32 instructions, half that without (this build forbids them)
+VALU_ISSUE_PEAK_G = 1024 * 2.4e9 / 4 / 1e9
+FP32_PEAK_TFLOPS = 157.3
 
 
 def log(*a):
@@ -107,6 +112,33 @@ def counted_traffic(workload_name: str, shape: dict):
     if d["launch"]["threads"] != shape["threads"] or d["launch"]["seg_rows"] != shape["seg_rows"]:
         return None
     return round(d["traffic_bytes"] / 1e9, 4)
+
+
+def counted_alu(workload_name: str, shape: dict, launch_us: float):
+    """The ALU side of the roofline from the committed SQ counters of the fused kernel (VALU
+    instructions per launch and their FP32/FP64 add, mul and fma mix), or None when they are for
+    another workload or launch shape, or the kernel sources changed since they were taken."""
+    path = os.path.join(ROOT, "profiles",
+                        f"k_fused_{workload_name}_t{shape['threads']}_s{shape['seg_rows']}_sq_counters.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("code_sha256") != kernel_code_digest() or d.get("workload") != workload_name:
+        return None
+    if d["launch"]["threads"] != shape["threads"] or d["launch"]["seg_rows"] != shape["seg_rows"]:
+        return None
+    c = d["counters"]
+    sec = launch_us * 1e-6
+    f32 = 64 * (c["SQ_INSTS_VALU_ADD_F32"] + c["SQ_INSTS_VALU_MUL_F32"] + 2 * c["SQ_INSTS_VALU_FMA_F32"])
+    f64 = 64 * (c["SQ_INSTS_VALU_ADD_F64"] + c["SQ_INSTS_VALU_MUL_F64"] + 2 * c["SQ_INSTS_VALU_FMA_F64"])
+    issue = c["SQ_INSTS_VALU"] / sec / 1e9
+    return {"bound": "alu", "unit": "TFLOP/s", "achieved": round(f32 / sec / 1e12, 2), "peak": FP32_PEAK_TFLOPS,
+            "frac": round(f32 / sec / 1e12 / FP32_PEAK_TFLOPS, 4),
+            "frac_of_nonpacked": round(f32 / sec / 1e12 / (FP32_PEAK_TFLOPS / 2), 4),
+            "fp32_flops_per_launch": f32, "fp64_flops_per_launch": f64,
+            "valu_issue": {"achieved": round(issue, 1), "peak": VALU_ISSUE_PEAK_G, "unit": "G wave instructions/s",
+                           "frac": round(issue / VALU_ISSUE_PEAK_G, 4)},
+            "source": os.path.relpath(path, ROOT)}
 
 
 def _db(path: str) -> str:
@@ -477,6 +509,7 @@ def main():
     roof = roofline(precision, sites, avg_ms, stored, copy_gbps)
     roof["traffic"] = counted_traffic(args.workload, shape)
     roof["traffic_unit"] = "GB per launch"
+    roof["alu"] = counted_alu(args.workload, shape, avg_ms * 1e3)
     log(f"bench: field kernel {avg_ms * 1e3:.2f} us/launch, body kernel {ib_ms * 1e3:.2f} us/launch, "
         f"{roof['achieved']:.0f} GB/s algorithmic ({roof['bytes_per_site']} B/site), frac {roof['frac']}")
     c4 = None

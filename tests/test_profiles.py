@@ -38,3 +38,30 @@ def test_counter_summaries_are_calibrated_against_a_copy():
         assert 1.9 < d["fetch_scale"] < 2.1 and 0.95 < d["write_scale"] < 1.05, j
         assert d["traffic_bytes"] > d["algorithmic_bytes"] > 0, j   # halo re-reads only add
         assert d["code_sha256"] and len(d["code_sha256"]) == 64, j
+
+
+def test_alu_side_of_the_roofline_comes_from_the_committed_counters():
+    """bench.py's roofline.alu: FP32 flops from the committed VALU mix (64 lanes x (add + mul +
+    2 fma) per issued instruction) over the launch time, and the VALU issue rate against one wave64
+    instruction per SIMD every 4 cycles at 2.4 GHz; both between 0 and 1 of their peaks."""
+    import importlib.util
+    import sys
+    spec = importlib.util.spec_from_file_location("bench_for_test", os.path.join(ROOT, "bench.py"))
+    b = importlib.util.module_from_spec(spec)
+    argv = sys.argv
+    try:
+        spec.loader.exec_module(b)
+    finally:
+        sys.argv = argv
+    for j in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_sq_counters.json"))):
+        d = json.load(open(j))
+        shape = {"threads": d["launch"]["threads"], "seg_rows": d["launch"]["seg_rows"]}
+        a = b.counted_alu(d["workload"], shape, 100.0)
+        if d["code_sha256"] != b.kernel_code_digest():
+            assert a is None, j
+            continue
+        c = d["counters"]
+        assert a["fp32_flops_per_launch"] == 64 * (c["SQ_INSTS_VALU_ADD_F32"] + c["SQ_INSTS_VALU_MUL_F32"]
+                                                   + 2 * c["SQ_INSTS_VALU_FMA_F32"]), j
+        assert 0 < a["frac"] < a["frac_of_nonpacked"] < 1 and 0 < a["valu_issue"]["frac"] < 1, (j, a)
+        assert b.VALU_ISSUE_PEAK_G == 614.4
