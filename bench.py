@@ -360,6 +360,9 @@ def c4_leg(args) -> dict:
            "ms_per_step": round(dt / args.c4_steps * 1e3, 5), "threads": shape["threads"],
            "seg_rows": shape["seg_rows"], "work_items": shape["n_items"],
            "roofline": roofline(precision, w.sites, avg_ms, stored, None), "body_update_us": round(ib_ms * 1e3, 3)}
+    out["roofline"]["traffic"] = counted_traffic("c4", shape)
+    out["roofline"]["traffic_unit"] = "GB per launch"
+    out["roofline"]["alu"] = counted_alu("c4", shape, avg_ms * 1e3)
     log(f"bench: c4 ensemble {out['value']} MLUPS, field kernel {avg_ms * 1e3:.1f} us, "
         f"frac {out['roofline']['frac']}")
     return out
