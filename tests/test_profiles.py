@@ -53,10 +53,19 @@ def test_alu_side_of_the_roofline_comes_from_the_committed_counters():
         spec.loader.exec_module(b)
     finally:
         sys.argv = argv
+    def trace_mean_us(workload):   # the field kernel's mean launch time in that workload's trace
+        for p in PROFILES:
+            t = open(p).read()
+            if "--kernel-trace" in t and f"--workload {workload} " in t:
+                for line in t.splitlines():
+                    if line.startswith("| `void lbk::k_fused"):
+                        return float(line.split("|")[4])
+        raise AssertionError(f"no kernel trace of {workload}")
+
     for j in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_sq_counters.json"))):
         d = json.load(open(j))
         shape = {"threads": d["launch"]["threads"], "seg_rows": d["launch"]["seg_rows"]}
-        a = b.counted_alu(d["workload"], shape, 100.0)
+        a = b.counted_alu(d["workload"], shape, trace_mean_us(d["workload"]))
         if d["code_sha256"] != b.kernel_code_digest():
             assert a is None, j
             continue
