@@ -950,6 +950,8 @@ static int create_impl(const lb_sim_params *sims, int n_sims, const lb_options *
         d.s2 = (float)((K1111 + 6 * K1122 - 4 * K1212 + K2222) / 8);
         d.s3 = (float)((K1111 - 2 * K1122 + 4 * K1212 + K2222) / 4);
         d.kap4 = (float)(0.25 * p.kappa);
+        d.m4D = (float)(-4.0 * p.D_p);
+        d.gk = (float)(p.Gamma * p.kappa);
         const Table &tb = *tabs[sp.tab];
         d.smax = (float)(p.P_clamp * p.P_clamp);
         d.inv_ds = (float)(kStiffSeg / (p.P_clamp * p.P_clamp));

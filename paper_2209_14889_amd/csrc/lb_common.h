@@ -32,6 +32,8 @@ struct SimDev {
     float s1, s2, s3;               // isotropic parts: (3K1111+2K1122+4K1212+3K2222) / 8,
                                     // (K1111+6K1122-4K1212+K2222) / 8, (K1111-2K1122+4K1212+K2222) / 4
     float kap4;                     // kappa / 4 (the Ericksen gradient term from half-differences)
+    float m4D, gk;                  // -4 D_p and Gamma kappa: the centre weight of the stress
+                                    // Laplacian and the Laplacian weight of the P right-hand side
     float smax, inv_ds;             // table range P_clamp^2 and intervals per unit s
     float A2max, A4max;             // a2/s and a4/s^2 at smax
     float inv_scale, scale;         // FP16 storage scale 2^-S and 2^S (1 for FP32)

@@ -134,11 +134,10 @@ template <> struct Pop<__half> {
 template <bool SCALED>
 __device__ __forceinline__ void collide_t(float d[9], float Fx, float Fy, float omega, float guo, float scale,
                                           float inv_scale, float &drho, float &ux, float &uy) {
-    float s0 = (d[0] + d[1]) + (d[2] + d[3]);
-    float s1 = (d[4] + d[5]) + (d[6] + d[7]);
-    drho = (s0 + s1) + d[8];
+    const float up = d[5] + d[6], dn = d[7] + d[8];   // the diagonal pairs with c_y = +1, -1
+    drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + up) + dn);
     float jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
-    float jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+    float jy = (d[2] - d[4]) + (up - dn);
     if (SCALED) {   // offsets held times the power-of-two storage scale: exact rescaling
         drho *= inv_scale;
         jx = fmaf(jx, inv_scale, 0.5f * Fx);
@@ -153,20 +152,28 @@ __device__ __forceinline__ void collide_t(float d[9], float Fx, float Fy, float 
     uy = jy * ir;
     // d' = (1 - omega) d + omega deq + src with, per direction n (t = c_n.u, g = c_n.F),
     //   deq = w_n (drho + rho (3 t + 4.5 t^2 - 1.5 u.u)),  src = guo w_n (3 (g - u.F) + 9 t g),
-    // gathered as w_n (C0 + t (a1 + a2 t) + g (b1 + b2 t)) with per-site a1, a2, C0
+    // gathered as w_n (C0 + t (a1 + a2 t) + g (b1 + b2 t)) with per-site a1, a2, C0.  Opposite
+    // directions share t^2 and t g and flip t and g, so each pair takes the even part
+    // E = C0 + t (a2 t + b2 g) and the odd part O = a1 t + b1 g once: w_n (E + O) and w_n (E - O).
     const float uu15 = 1.5f * (ux * ux + uy * uy);
     const float uF = ux * Fx + uy * Fy;
     const float orho = omega * rho;
     const float a1 = 3.0f * orho, a2 = 4.5f * orho, b1 = 3.0f * guo, b2 = 9.0f * guo;
     const float C0 = omega * drho - orho * uu15 - b1 * uF;
     const float keep = 1.0f - omega;
-#pragma unroll
-    for (int n = 0; n < 9; ++n) {
-        const float t = kCX[n] * ux + kCY[n] * uy;
-        const float g = kCX[n] * Fx + kCY[n] * Fy;
-        const float r = fmaf(t, fmaf(a2, t, a1), fmaf(g, fmaf(b2, t, b1), C0));
-        d[n] = fmaf(keep, d[n], (SCALED ? kW[n] * scale : kW[n]) * r);
-    }
+    const float ws = SCALED ? kW[1] * scale : kW[1], wd = SCALED ? kW[5] * scale : kW[5];
+    d[0] = fmaf(keep, d[0], (SCALED ? kW[0] * scale : kW[0]) * C0);
+    auto pair = [&](int n, int m, float t, float g, float w) {   // m: the direction opposite to n
+        const float E = fmaf(t, fmaf(a2, t, b2 * g), C0);
+        const float O = fmaf(a1, t, b1 * g);
+        const float wE = w * E, wO = w * O;
+        d[n] = fmaf(keep, d[n], wE + wO);
+        d[m] = fmaf(keep, d[m], wE - wO);
+    };
+    pair(1, 3, ux, Fx, ws);
+    pair(2, 4, uy, Fy, ws);
+    pair(5, 7, ux + uy, Fx + Fy, wd);
+    pair(6, 8, uy - ux, Fy - Fx, wd);
 }
 
 __device__ __forceinline__ void collide(float d[9], float Fx, float Fy, float omega, float guo,
@@ -249,7 +256,9 @@ __device__ __forceinline__ Grad grad_v(float hxe, float hxw, float hxn, float hx
 // right-hand side of eqStiffCons (corotational derivative) for one component set:
 // -(v.grad)X - (Omega X - X Omega) + C~(Psi - X/eta_p) + D_p lap X.
 // X[c] centre, e/w/n/s neighbours of each component.
-// hx, hy: half the velocity, so the central differences need no halving.
+// hx, hy: half the velocity.  The advection and diffusion terms are one five-point stencil,
+// D lap X - (v.grad) X = (D - hx) Xe + (D + hx) Xw + (D - hy) Xn + (D + hy) Xs - 4 D X, whose
+// weights are shared by the three components.
 __device__ __forceinline__ void rhs_sigma(const SimDev &S, const Stiff &k, const Grad &g, float hx, float hy,
                                           const float X[3], const float Xe[3], const float Xw[3],
                                           const float Xn[3], const float Xs[3], float R[3]) {
@@ -258,16 +267,13 @@ __device__ __forceinline__ void rhs_sigma(const SimDev &S, const Stiff &k, const
     float c = g.psi2 - S.inv_eta * X[2];
     float C0, C1, C2;
     stiff_apply(S, k, a, b, c, C0, C1, C2);
-    float J0 = 2.0f * g.om * X[2];
-    float J2 = g.om * (X[1] - X[0]);
-    float Cv[3] = {C0, C1, C2};
-    float Jv[3] = {J0, -J0, J2};
+    const float J0 = 2.0f * g.om * X[2];
+    const float J2 = g.om * (X[1] - X[0]);
+    const float Bv[3] = {C0 - J0, C1 + J0, C2 - J2};
+    const float we = S.D - hx, ww = S.D + hx, wn = S.D - hy, ws = S.D + hy;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        float adv = hx * (Xe[q] - Xw[q]) + hy * (Xn[q] - Xs[q]);
-        float lap = ((Xe[q] + Xw[q]) + (Xn[q] + Xs[q])) - 4.0f * X[q];
-        R[q] = Cv[q] - Jv[q] - adv + S.D * lap;
-    }
+    for (int q = 0; q < 3; ++q)
+        R[q] = fmaf(we, Xe[q], fmaf(ww, Xw[q], fmaf(wn, Xn[q], fmaf(ws, Xs[q], fmaf(S.m4D, X[q], Bv[q])))));
 }
 
 // Polarization storage follows the population storage.  With FP32 populations (the full-precision
@@ -310,19 +316,20 @@ __device__ __forceinline__ PLocal p_local(const SimDev &S, const PT Y[2], const 
 }
 
 // right-hand side of eqBE for the stored offsets: -(v.grad)Y - Omega P + xi Psi P - Gamma h(P),
-// h = (alpha + beta |P|^2) P - kappa lap P (pref is constant, so the gradients of P are those of Y)
+// h = (alpha + beta |P|^2) P - kappa lap P (pref is constant, so the gradients of P are those of Y).
+// The advection and the Gamma kappa lap P part of -Gamma h are one stencil on the neighbour
+// differences: (Gk - hx) de + (Gk + hx) dw + (Gk - hy) dn + (Gk + hy) ds, Gk = Gamma kappa.
 template <typename PT>
 __device__ __forceinline__ void rhs_P(const SimDev &S, const Grad &g, float hx, float hy, const PT Y[2],
                                       const PT Ye[2], const PT Yw[2], const PT Yn[2], const PT Ys[2], PT R[2]) {
     const PLocal L = p_local(S, Y, Ye, Yw, Yn, Ys);
-    const float lap0 = (L.d[0][0] + L.d[1][0]) + (L.d[2][0] + L.d[3][0]);
-    const float lap1 = (L.d[0][1] + L.d[1][1]) + (L.d[2][1] + L.d[3][1]);
-    const float h0 = L.a * L.c[0] - S.kappa * lap0;
-    const float h1 = L.a * L.c[1] - S.kappa * lap1;
-    const float adv0 = hx * (L.d[0][0] - L.d[1][0]) + hy * (L.d[2][0] - L.d[3][0]);
-    const float adv1 = hx * (L.d[0][1] - L.d[1][1]) + hy * (L.d[2][1] - L.d[3][1]);
-    R[0] = (PT)(-adv0 - g.om * L.c[1] + S.xi * (g.psi0 * L.c[0] + g.psi2 * L.c[1]) - S.Gamma * h0);
-    R[1] = (PT)(-adv1 + g.om * L.c[0] + S.xi * (g.psi2 * L.c[0] + g.psi1 * L.c[1]) - S.Gamma * h1);
+    const float we = S.gk - hx, ww = S.gk + hx, wn = S.gk - hy, ws = S.gk + hy;
+    const float ga = S.Gamma * L.a;
+    float T[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) T[q] = fmaf(we, L.d[0][q], fmaf(ww, L.d[1][q], fmaf(wn, L.d[2][q], ws * L.d[3][q])));
+    R[0] = (PT)fmaf(S.xi, fmaf(g.psi0, L.c[0], g.psi2 * L.c[1]), fmaf(-g.om, L.c[1], fmaf(-ga, L.c[0], T[0])));
+    R[1] = (PT)fmaf(S.xi, fmaf(g.psi2, L.c[0], g.psi1 * L.c[1]), fmaf(g.om, L.c[0], fmaf(-ga, L.c[1], T[1])));
 }
 
 // Ericksen stress at a site (Sec. II C 1, with kappa on the gradient term), from the stored

@@ -753,16 +753,16 @@ __global__ __launch_bounds__(T, (WALLS || !std::is_same<HT, __half>::value) ? 3 
             if (j >= 4 && colC) {
                 const bool clo = walls && rm2 == 0u, chi = walls && rm2 == ytop;
                 const int bn = chi ? b2 : b1, bs = clo ? b2 : b3;
-                float Fx = 0.5f * (rS[b2][0][te] - rS[b2][0][tw]) + 0.5f * (rS[bn][2][tid] - rS[bs][2][tid]);
-                float Fy = 0.5f * (rS[b2][2][te] - rS[b2][2][tw]) + 0.5f * (rS[bn][1][tid] - rS[bs][1][tid]);
+                // twice the divergence of the stresses (central differences), halved once
+                float fx = (rS[b2][0][te] - rS[b2][0][tw]) + (rS[bn][2][tid] - rS[bs][2][tid]);
+                float fy = (rS[b2][2][te] - rS[b2][2][tw]) + (rS[bn][1][tid] - rS[bs][1][tid]);
                 if (POL && S.ericksen) {
                     const float exn = chi ? exy2 : exy1, exs = clo ? exy2 : exy3;
                     const float eyn = chi ? eyy2 : eyy1, eys = clo ? eyy2 : eyy3;
-                    Fx += 0.5f * (rE[o0][0][te] - rE[o0][0][tw]) + 0.5f * (exn - exs);
-                    Fy += 0.5f * (rE[o0][1][te] - rE[o0][1][tw]) + 0.5f * (eyn - eys);
+                    fx += (rE[o0][0][te] - rE[o0][0][tw]) + (exn - exs);
+                    fy += (rE[o0][1][te] - rE[o0][1][tw]) + (eyn - eys);
                 }
-                Fx += S.gx;
-                Fy += S.gy;
+                float Fx = fmaf(0.5f, fx, S.gx), Fy = fmaf(0.5f, fy, S.gy);
                 if (nib > 0)
                     ib_force_list(sIB, nib, (int)nx, (int)ny, (int)x, (int)rm2, Fx, Fy);
                 else if (nib < 0)
