@@ -490,6 +490,7 @@ struct lb_handle {
     bool any_pol = false;     // some simulation has a polarization field; if none, P stays 0 and the
                               // fused variant without the P and Ericksen work runs
     int n_items = 0;
+    int cus = 1;   // compute units of the device (the fused kernel's first-round order)
     float tuned_ms = 0.f;
     // graph replay: executable graphs of graph_chunk steps and of every power of two below it, each
     // captured from parity 0 (even lengths, so a replay ends at parity 0 again)
@@ -582,7 +583,7 @@ int launch_step(lb_handle *h, bool timed) {
     }
     if (h->opt.kernel == 0) {
         HIPCHK(launch_fused(h->fused_T, fp16, h->any_walls, h->any_pol, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
-                            h->n_items, h->cur, h->d_t));
+                            h->n_items, h->cur, h->d_t, h->cus));
     } else {
         HIPCHK(launch_multipass(fp16, (int)h->plan.site_blk.size(), h->stream, h->d_sims, h->d_bodies, h->d_site,
                                 h->cur, h->d_t));
@@ -699,11 +700,12 @@ void tune_store(const std::string &path, uint64_t key, int T, int seg, int grid,
 // buffer `cur` and writes the other one, so repeating it without flipping the parity changes
 // nothing (the step counter it advances is restored afterwards).
 int choose_fused_config(lb_handle *h) {
-    if (h->opt.kernel != 0) return LB_OK;
-    const bool fp16 = h->opt.precision == 1;
     int dev = 0, cus = 256;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    h->cus = std::max(1, cus);
+    if (h->opt.kernel != 0) return LB_OK;
+    const bool fp16 = h->opt.precision == 1;
     // work-group width: lattices no wider than 64 or 128 run as full-width strips of that many
     // lanes (no halo lanes and no idle waves); wider ones as 248-column strips of 256 lanes
     auto model_T = [&]() {
@@ -762,7 +764,7 @@ int choose_fused_config(lb_handle *h) {
         if (rc) return rc;
         for (int r = 0; r < 30; ++r)
             HIPCHK(launch_fused(cand.front().T, fp16, h->any_walls, h->any_pol, h->fused_grid, h->stream, h->d_sims, h->d_bodies,
-                                h->d_items, h->n_items, h->cur, h->d_t));
+                                h->d_items, h->n_items, h->cur, h->d_t, h->cus));
     }
     std::vector<float> tbest(cand.size(), 1e30f);
     for (int pass = 0; pass < 2; ++pass) {
@@ -771,11 +773,11 @@ int choose_fused_config(lb_handle *h) {
             int rc = upload_items(h, c.T, c.seg, c.grid);
             if (rc) return rc;
             HIPCHK(launch_fused(c.T, fp16, h->any_walls, h->any_pol, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
-                                h->n_items, h->cur, h->d_t));
+                                h->n_items, h->cur, h->d_t, h->cus));
             HIPCHK(hipEventRecord(e0, h->stream));
             for (int r = 0; r < 8; ++r)
                 HIPCHK(launch_fused(c.T, fp16, h->any_walls, h->any_pol, h->fused_grid, h->stream, h->d_sims, h->d_bodies, h->d_items,
-                                    h->n_items, h->cur, h->d_t));
+                                    h->n_items, h->cur, h->d_t, h->cus));
             HIPCHK(hipEventRecord(e1, h->stream));
             HIPCHK(hipEventSynchronize(e1));
             float ms = 0;

@@ -52,31 +52,41 @@ __device__ __forceinline__ double pull_factor(const BodyDev &B, double t) {
     return 1.0 / (1.0 + exp(-(t - B.t_on) / B.width)) - 1.0 / (1.0 + exp(-(t - B.t_off) / B.width));
 }
 
-// v at point R from the body's velocity patch (origin ox, oy); flags reads outside the patch
-__device__ __forceinline__ void interp_patch(const BodyDev &B, int ox, int oy, double Rx, double Ry,
+// v at point R from a body's velocity patch V (side ps, origin ox, oy; the x plane, then the y
+// plane), in global memory or a copy in LDS; flags reads outside the patch
+__device__ __forceinline__ void interp_patch(const float *V, int ps, int ox, int oy, double Rx, double Ry,
                                              double &vx, double &vy, bool &bad) {
     int ix, iy;
     float wx[4], wy[4];
     phi4(Rx, ix, wx);
     phi4(Ry, iy, wy);
-    const size_t pp = (size_t)B.ps * B.ps;
+    const size_t pp = (size_t)ps * ps;
     vx = 0.0;
     vy = 0.0;
     const int px0 = ix - ox, py0 = iy - oy;
-    if (px0 < 0 || py0 < 0 || px0 + 3 >= B.ps || py0 + 3 >= B.ps) {
+    if (px0 < 0 || py0 < 0 || px0 + 3 >= ps || py0 + 3 >= ps) {
         bad = true;
         return;
     }
     for (int j = 0; j < 4; ++j) {
         double ax = 0.0, ay = 0.0;
-        const size_t q = (size_t)(py0 + j) * B.ps + px0;
+        const size_t q = (size_t)(py0 + j) * ps + px0;
         for (int i = 0; i < 4; ++i) {
-            ax += (double)wx[i] * (double)B.vib[q + i];
-            ay += (double)wx[i] * (double)B.vib[pp + q + i];
+            ax += (double)wx[i] * (double)V[q + i];
+            ay += (double)wx[i] * (double)V[pp + q + i];
         }
         vx += (double)wy[j] * ax;
         vy += (double)wy[j] * ay;
     }
+}
+
+// Heun step of one node through the velocity patch V: R + (v(R) + v(R + v(R))) / 2
+__device__ __forceinline__ void heun_node(const float *V, int ps, int ox, int oy, double2 &R, bool &bad) {
+    double v1x, v1y, v2x, v2y;
+    interp_patch(V, ps, ox, oy, R.x, R.y, v1x, v1y, bad);
+    interp_patch(V, ps, ox, oy, R.x + v1x, R.y + v1y, v2x, v2y, bad);
+    R.x += 0.5 * (v1x + v2x);
+    R.y += 0.5 * (v1y + v2y);
 }
 
 // derivative of cos(gamma_j) with respect to e1 = R_{j-1} - R_j (d1) and e2 = R_{j+1} - R_j (d2)
@@ -189,13 +199,7 @@ __global__ __launch_bounds__(256) void k_ib_nodes(const SimDev *__restrict__ sim
     }
     for (int a = tid; a < n; a += 256) {
         double2 R = Rc[a];
-        if (ADVANCE) {
-            double v1x, v1y, v2x, v2y;
-            interp_patch(B, ox, oy, R.x, R.y, v1x, v1y, bad);
-            interp_patch(B, ox, oy, R.x + v1x, R.y + v1y, v2x, v2y, bad);
-            R.x += 0.5 * (v1x + v2x);
-            R.y += 0.5 * (v1y + v2y);
-        }
+        if (ADVANCE) heun_node(B.vib, B.ps, ox, oy, R, bad);
         sR[a] = R;
     }
     __syncthreads();
@@ -397,13 +401,7 @@ __global__ __launch_bounds__(256) void k_ib_step(const SimDev *__restrict__ sims
     double mnx = 1e300, mny = 1e300, mxx = -1e300, mxy = -1e300, cx = 0.0, cy = 0.0;
     for (int a = tid; a < n; a += 256) {
         double2 R = Rc[a];
-        if (ADVANCE) {
-            double v1x, v1y, v2x, v2y;
-            interp_patch(B, ox, oy, R.x, R.y, v1x, v1y, bad);
-            interp_patch(B, ox, oy, R.x + v1x, R.y + v1y, v2x, v2y, bad);
-            R.x += 0.5 * (v1x + v2x);
-            R.y += 0.5 * (v1y + v2y);
-        }
+        if (ADVANCE) heun_node(B.vib, B.ps, ox, oy, R, bad);
         sR[a] = R;
         mnx = fmin(mnx, R.x);
         mny = fmin(mny, R.y);
@@ -528,7 +526,7 @@ __device__ __forceinline__ void inc_row(unsigned &r, unsigned ny) { r = (r + 1u 
 template <int T, typename HT, bool WALLS, bool POL>
 __global__ __launch_bounds__(T, (WALLS || !std::is_same<HT, __half>::value) ? 3 : 4) void k_fused(const SimDev *__restrict__ sims, const BodyDev *__restrict__ bodies,
                                              const WorkItem *__restrict__ items, int n_items, int cur,
-                                             int *__restrict__ d_t) {
+                                             int *__restrict__ d_t, int cus) {
     // row-exchange rings; values a thread needs only from its own column one row below live in
     // registers (the "carried" row of the previous iteration)
     typedef typename PolOf<HT>::T PT;   // polarization storage: FP32 offsets with FP16 populations, else FP64
@@ -889,10 +887,17 @@ __global__ __launch_bounds__(T, (WALLS || !std::is_same<HT, __half>::value) ? 3 
         // two iterations per trip with the register sets swapped, so no values are copied.  The
         // waves' issue priority falls in thirds as the item progresses: a compute unit's SIMDs are
         // shared by several work-groups, and under the hardware's oldest-first arbitration the
-        // last-dispatched ones would otherwise trail alone, at low VALU use, at the end.
-        const int q1 = niter / 3, q2 = (2 * niter) / 3;
+        // last-dispatched ones would otherwise trail alone, at low VALU use, at the end.  Work-groups
+        // of the first round are dealt to the units in turn, so work-group b is the (b / cus)-th on
+        // its unit; the later ones hold each priority two row iterations longer per older
+        // work-group.  Items that touch a body (their spread-force reads make them the slowest)
+        // keep the top priority, so they no longer finish last.
+        const int lag = 2 * min(3, (int)blockIdx.x / cus);
+        const int q1 = niter / 3 + lag, q2 = (2 * niter) / 3 + lag;
         for (int j = 0; j < niter; j += 2) {
-            if (j >= q2)
+            if (nib != 0)
+                __builtin_amdgcn_s_setprio(3);
+            else if (j >= q2)
                 __builtin_amdgcn_s_setprio(0);
             else if (j >= q1)
                 __builtin_amdgcn_s_setprio(1);
@@ -1364,7 +1369,7 @@ hipError_t launch_ib(bool advance, int nbodies, int ntiles, hipStream_t st, cons
 }
 
 // the kernel for (work-group size, storage type, walls, polarization)
-typedef void (*FusedFn)(const SimDev *, const BodyDev *, const WorkItem *, int, int, int *);
+typedef void (*FusedFn)(const SimDev *, const BodyDev *, const WorkItem *, int, int, int *, int);
 template <int T, typename HT>
 static FusedFn fused_fn_t(bool walls, bool pol) {
     if (walls) return pol ? k_fused<T, HT, true, true> : k_fused<T, HT, true, false>;
@@ -1378,10 +1383,10 @@ static FusedFn fused_fn(int T, bool fp16, bool walls, bool pol) {
 }
 
 hipError_t launch_fused(int T, bool fp16, bool walls, bool pol, int grid, hipStream_t st, const SimDev *sims,
-                        const BodyDev *bodies, const WorkItem *items, int n_items, int cur, int *d_t) {
+                        const BodyDev *bodies, const WorkItem *items, int n_items, int cur, int *d_t, int cus) {
     FusedFn f = fused_fn(T, fp16, walls, pol);
-    if (!f) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(f, dim3(grid), dim3(T), 0, st, sims, bodies, items, n_items, cur, d_t);
+    if (!f || cus < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(f, dim3(grid), dim3(T), 0, st, sims, bodies, items, n_items, cur, d_t, cus);
     return hipGetLastError();
 }
 

@@ -12,9 +12,10 @@ void set_last_error(const char *msg);
 hipError_t launch_ib(bool advance, int nbodies, int ntiles, hipStream_t st, const SimDev *sims, BodyDev *bodies,
                      const int2 *blk, int cur, const int *d_t, int *d_status);
 // walls: the variant with wall handling (needed when any simulation of the launch has walls);
-// pol: the variant with the polarization field (needed unless P is zero in every simulation)
+// pol: the variant with the polarization field (needed unless P is zero in every simulation);
+// cus: the device's compute units (work-groups of the first round are dealt to them in turn)
 hipError_t launch_fused(int T, bool fp16, bool walls, bool pol, int grid, hipStream_t st, const SimDev *sims,
-                        const BodyDev *bodies, const WorkItem *items, int n_items, int cur, int *d_t);
+                        const BodyDev *bodies, const WorkItem *items, int n_items, int cur, int *d_t, int cus);
 // resident fused work-groups per compute unit for work-group size T
 int fused_blocks_per_cu(int T, bool fp16, bool walls, bool pol);
 hipError_t launch_multipass(bool fp16, int nblocks, hipStream_t st, const SimDev *sims, const BodyDev *bodies,
