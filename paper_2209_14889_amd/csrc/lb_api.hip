@@ -616,11 +616,88 @@ int launch_step(lb_handle *h, bool timed) {
     return LB_OK;
 }
 
+// the work item of work-group b among n (the fused kernel's xcd_remap: each XCD a contiguous run)
+int item_of_block(int b, int n) {
+    const int q = n >> 3, r = n & 7, x = b & 7, k = b >> 3;
+    return x * q + std::min(x, r) + k;
+}
+
+// do the periodic intervals [a, a + la) and [b, b + lb) on a ring of n sites intersect? (the
+// fused kernel's ring_overlap)
+bool ring_overlap_h(int a, int la, int b, int lb, int n) {
+    if (la >= n || lb >= n) return true;
+    int d = b - a;
+    d = d < 0 ? d + n : d;
+    if (d < la) return true;
+    int e = a - b;
+    e = e < 0 ? e + n : e;
+    return e < lb;
+}
+
+int wrap_h(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+// A launch of at most four work-groups per compute unit deals them to the units in turn: work-group
+// b runs on unit b mod cus as its (b / cus)-th, so the units from n - 3 cus on hold three.  Items
+// that reach a body's force patch are the slowest (their spread-force reads), and a unit with two
+// of them finishes last.  Each is moved to the first work-group of its own unit, the three-item
+// units first, by swapping it with the item there.  The patches are those of the current step;
+// bodies drift by a small fraction of a site per step, so the order holds for long runs, and it
+// only ever changes which work-group takes an item, never the item.
+int place_body_items(lb_handle *h, std::vector<WorkItem> &items) {
+    const int n = (int)items.size(), cus = h->cus;
+    if (h->hb.empty() || n <= cus || n > 4 * cus) return LB_OK;
+    struct Patch {
+        int sim, ox, oy, ps;
+    };
+    std::vector<Patch> patches;
+    for (size_t b = 0; b < h->hb.size(); ++b) {
+        int o[2] = {0, 0};
+        HIPCHK(hipMemcpy(o, h->hb[b].origin + 4 * h->cur + 2, sizeof o, hipMemcpyDeviceToHost));
+        patches.push_back(Patch{h->plan.bodies[b].sim, o[0], o[1], h->plan.bodies[b].ps});
+    }
+    std::vector<char> slow(n, 0);
+    for (int i = 0; i < n; ++i) {
+        const WorkItem &wi = items[i];
+        const int nx = h->plan.sims[wi.sim].nx, ny = h->plan.sims[wi.sim].ny;
+        const int lanes = wi.full ? wi.w : wi.w + 2 * kHalo;
+        for (const Patch &p : patches)
+            if (p.sim == wi.sim && ring_overlap_h(p.ox, p.ps, wi.full ? 0 : wrap_h(wi.x0 - kHalo, nx), lanes, nx) &&
+                ring_overlap_h(p.oy, p.ps, wrap_h(wi.y0 - 2, ny), wi.l + 4, ny))
+                slow[i] = 1;
+    }
+    std::vector<int> of_block(n), block_of(n);   // item index taken by each work-group, and back
+    for (int b = 0; b < n; ++b) {
+        of_block[b] = item_of_block(b, n);
+        block_of[of_block[b]] = b;
+    }
+    const int light = std::max(0, n - 3 * cus);   // first work-group of the first three-item unit
+    int next = 0;
+    for (int i = 0; i < n && next < cus; ++i) {
+        if (!slow[i]) continue;
+        const int t = (light + next++) % cus;   // the first work-groups, three-item units first
+        const int b = block_of[i], j = of_block[t];
+        std::swap(of_block[b], of_block[t]);
+        block_of[i] = t;
+        block_of[j] = b;
+    }
+    std::vector<WorkItem> placed(n);
+    for (int b = 0; b < n; ++b) placed[item_of_block(b, n)] = items[of_block[b]];
+    items.swap(placed);
+    return LB_OK;
+}
+
 // grid: 0 = one work-group per item; > 0 = persistent grid of that many work-groups (a multiple
 // of 8, so each XCD keeps a contiguous run of items) looping over the item table
 int upload_items(lb_handle *h, int T, int seg, int grid = 0) {
     std::vector<WorkItem> items = build_items(h->plan.sims, T, seg);
     if (items.size() > h->plan.items.size()) return fail(LB_EINVAL, "internal: work-item table overflow");
+    if (grid <= 0 || grid >= (int)items.size()) {
+        const int rc = place_body_items(h, items);
+        if (rc) return rc;
+    }
     HIPCHK(hipMemcpyAsync(h->d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     h->fused_T = T;
