@@ -889,11 +889,11 @@ __global__ __launch_bounds__(T, (WALLS || !std::is_same<HT, __half>::value) ? 3 
         // shared by several work-groups, and under the hardware's oldest-first arbitration the
         // last-dispatched ones would otherwise trail alone, at low VALU use, at the end.  When the
         // whole grid is one round of at most four work-groups per unit, dealt to the units in turn,
-        // work-group b is the (b / cus)-th on its unit, and the later ones hold each priority two
+        // work-group b is the (b / cus)-th on its unit, and the later ones hold each priority three
         // row iterations longer per older work-group (longer grids start their work-groups as
         // others finish, and gain nothing from it).  Items that touch a body (their spread-force
         // reads make them the slowest) keep the top priority, so they no longer finish last.
-        const int lag = (int)gridDim.x <= 4 * cus ? 2 * min(3, (int)blockIdx.x / cus) : 0;
+        const int lag = (int)gridDim.x <= 4 * cus ? 3 * min(3, (int)blockIdx.x / cus) : 0;
         const int q1 = niter / 3 + lag, q2 = (2 * niter) / 3 + lag;
         for (int j = 0; j < niter; j += 2) {
             if (nib != 0)
