@@ -53,7 +53,7 @@ __device__ __forceinline__ double pull_factor(const BodyDev &B, double t) {
 }
 
 // v at point R from a body's velocity patch V (side ps, origin ox, oy; the x plane, then the y
-// plane), in global memory or a copy in LDS; flags reads outside the patch
+// plane); flags reads outside the patch
 __device__ __forceinline__ void interp_patch(const float *V, int ps, int ox, int oy, double Rx, double Ry,
                                              double &vx, double &vy, bool &bad) {
     int ix, iy;
