@@ -419,7 +419,12 @@ Plan make_plan(const lb_sim_params *sims, int n_sims, const Opt &o) {
 
 // Work items: a lattice no wider than T is one full-width strip (no halo lanes); a wider one is cut
 // into strips of T-8 columns and one narrower remainder, so only the remainder's block carries
-// idle lanes; segments of about seg rows.
+// idle lanes; segments of about seg rows.  When the last full strip and the remainder, cut into
+// two equal strips instead, take no more waves (for 2048 columns at T = 256: 248 + 64 columns in
+// 4 + 2 waves, or 156 + 156 in 3 + 3), they are: more of the items then leave a wave idle, and one
+// such item on each unit with four work-groups takes a wave off the busiest units.
+int strip_waves(int w) { return (w + 2 * kHalo + 63) / 64; }
+
 std::vector<WorkItem> build_items(const std::vector<SimPlan> &sims, int T, int seg) {
     std::vector<WorkItem> items;
     const int W = T - 2 * kHalo;
@@ -427,13 +432,24 @@ std::vector<WorkItem> build_items(const std::vector<SimPlan> &sims, int T, int s
         int nx = sims[s].nx, ny = sims[s].ny;
         const bool full = nx <= T;
         int ns = full ? 1 : (nx + W - 1) / W;
+        std::vector<int> sx0, sw;   // strip origins and widths
+        for (int k = 0; k < ns; ++k) {
+            sx0.push_back(full ? 0 : k * W);
+            sw.push_back(full ? nx : std::min(nx, (k + 1) * W) - k * W);
+        }
+        if (!full && ns >= 2) {
+            const int rem = sw[ns - 1], wa = (W + rem) / 2, wb = W + rem - wa;
+            if (rem < W && strip_waves(wa) + strip_waves(wb) <= strip_waves(W) + strip_waves(rem)) {
+                sw[ns - 2] = wa;
+                sx0[ns - 1] = sx0[ns - 2] + wa;
+                sw[ns - 1] = wb;
+            }
+        }
         int ng = std::max(1, (ny + seg - 1) / seg);
         for (int g = 0; g < ng; ++g) {
             int y0 = (int)((long)g * ny / ng), y1 = (int)((long)(g + 1) * ny / ng);
-            for (int k = 0; k < ns; ++k) {
-                int x0 = full ? 0 : k * W, x1 = full ? nx : std::min(nx, (k + 1) * W);
-                items.push_back(WorkItem{(int)s, x0, y0, x1 - x0, y1 - y0, full ? 1 : 0, 0, 0});
-            }
+            for (int k = 0; k < ns; ++k)
+                items.push_back(WorkItem{(int)s, sx0[k], y0, sw[k], y1 - y0, full ? 1 : 0, 0, 0});
         }
     }
     return items;
@@ -674,14 +690,40 @@ int place_body_items(lb_handle *h, std::vector<WorkItem> &items) {
         block_of[of_block[b]] = b;
     }
     const int light = std::max(0, n - 3 * cus);   // first work-group of the first three-item unit
-    int next = 0;
-    for (int i = 0; i < n && next < cus; ++i) {
-        if (!slow[i]) continue;
-        const int t = (light + next++) % cus;   // the first work-groups, three-item units first
+    auto move = [&](int i, int t) {   // item i to work-group t, the item there to i's work-group
         const int b = block_of[i], j = of_block[t];
         std::swap(of_block[b], of_block[t]);
         block_of[i] = t;
         block_of[j] = b;
+    };
+    std::vector<char> hasBody(cus, 0);
+    int next = 0;
+    for (int i = 0; i < n && next < cus; ++i) {
+        if (!slow[i]) continue;
+        const int t = (light + next++) % cus;   // the first work-groups, three-item units first
+        move(i, t);
+        hasBody[t] = 1;
+    }
+    // then the items with an idle wave, one on each four-item unit that runs no body item (as its
+    // second work-group), so that no unit runs four items of full waves where this can be avoided;
+    // each goes to a unit of its own XCD (work-group b runs on XCD b mod 8, and so do all of a
+    // unit's work-groups when cus is a multiple of 8), where its neighbours' rows are in the L2
+    int maxw = 0;
+    for (const WorkItem &wi : items) maxw = std::max(maxw, wi.full ? (wi.w + 63) / 64 : strip_waves(wi.w));
+    std::vector<char> busy(hasBody);   // units that already run a body item or an idle-wave item
+    for (int i = 0; i < n; ++i) {
+        const WorkItem &wi = items[i];
+        if (slow[i] || wi.full || strip_waves(wi.w) >= maxw) continue;
+        const int x = block_of[i] & 7;
+        int t = -1;
+        for (int c = (cus % 8 == 0 ? x : 0); c < light && cus + c < n; c += (cus % 8 == 0 ? 8 : 1))
+            if (!busy[c]) {
+                t = c;
+                break;
+            }
+        if (t < 0) continue;
+        move(i, cus + t);
+        busy[t] = 1;
     }
     std::vector<WorkItem> placed(n);
     for (int b = 0; b < n; ++b) placed[item_of_block(b, n)] = items[of_block[b]];
