@@ -85,11 +85,14 @@ KERNEL_SOURCES = ["paper_2209_14889_amd/csrc/lb_kernels.hip", "paper_2209_14889_
 
 
 def kernel_code_digest() -> str:
-    """sha256 of the fused kernel's sources with comments and white space removed: only a change of
-    the code itself makes committed counters stale."""
+    """sha256 of the fused kernel's sources with comments and white space removed, and of the flags
+    they are compiled with: only a change of the code or of its compilation makes committed
+    counters stale."""
     import hashlib
     import re
+    from paper_2209_14889_amd import build as _build
     h = hashlib.sha256()
+    h.update(" ".join(_build.flags_for("lb_kernels.hip")).encode())
     for p in KERNEL_SOURCES:
         t = open(os.path.join(ROOT, p)).read()
         t = re.sub(r"/\*.*?\*/", " ", t, flags=re.S)

@@ -17,12 +17,23 @@ HIPCC_FLAGS = [
     "-Wall", "-Wno-unused-function",
 ]
 
+# per-source additions.  The compiler's iterative occupancy scheduler for the lattice kernels: the
+# one-launch body update then takes 84 VGPRs instead of 116 and 0.25 us less, a coupled step on the
+# 2048^2 FP16 case 0.6 us less (99.4 against 100.0 us, alternating runs on one device); the field
+# kernel's time does not change measurably.
+SOURCE_FLAGS = {"lb_kernels.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-maxocc"]}
+
+
+def flags_for(src: str) -> list:
+    """The hipcc flags one source is compiled with."""
+    return [*HIPCC_FLAGS, *SOURCE_FLAGS.get(src, [])]
+
 
 def build(verbose: bool = False) -> str:
     objs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmd = ["hipcc", *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+        cmd = ["hipcc", *flags_for(src), "-I", os.path.join(ROOT, "include"), "-I", CSRC,
                "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
