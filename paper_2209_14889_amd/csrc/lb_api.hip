@@ -711,6 +711,7 @@ int place_body_items(lb_handle *h, std::vector<WorkItem> &items) {
     int maxw = 0;
     for (const WorkItem &wi : items) maxw = std::max(maxw, wi.full ? (wi.w + 63) / 64 : strip_waves(wi.w));
     std::vector<char> busy(hasBody);   // units that already run a body item or an idle-wave item
+    std::vector<char> done(n, 0);
     for (int i = 0; i < n; ++i) {
         const WorkItem &wi = items[i];
         if (slow[i] || wi.full || strip_waves(wi.w) >= maxw) continue;
@@ -724,6 +725,18 @@ int place_body_items(lb_handle *h, std::vector<WorkItem> &items) {
         if (t < 0) continue;
         move(i, cus + t);
         busy[t] = 1;
+        done[i] = 1;
+    }
+    // the XCDs hold unequal numbers of such items and of free four-item units: the rest go to the
+    // four-item units still without one, on any XCD
+    int c = 0;
+    for (int i = 0; i < n; ++i) {
+        const WorkItem &wi = items[i];
+        if (done[i] || slow[i] || wi.full || strip_waves(wi.w) >= maxw) continue;
+        while (c < light && cus + c < n && busy[c]) ++c;
+        if (c >= light || cus + c >= n) break;
+        move(i, cus + c);
+        busy[c] = 1;
     }
     std::vector<WorkItem> placed(n);
     for (int b = 0; b < n; ++b) placed[item_of_block(b, n)] = items[of_block[b]];
