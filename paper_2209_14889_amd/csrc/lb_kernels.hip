@@ -600,10 +600,11 @@ __global__ __launch_bounds__(T, (WALLS || !std::is_same<HT, __half>::value) ? 3 
         }
 
         // wrapped row indices relative to the front row f of the current iteration
-        const int f0 = wi.y0 - 4;
-        unsigned rp1 = (unsigned)wrapi(f0 + 1, (int)ny), r0 = (unsigned)wrapi(f0, (int)ny);
-        unsigned rm1 = (unsigned)wrapi(f0 - 1, (int)ny), rm2 = (unsigned)wrapi(f0 - 2, (int)ny);
-        unsigned rm3 = (unsigned)wrapi(f0 - 3, (int)ny), rm4 = (unsigned)wrapi(f0 - 4, (int)ny);
+        // (the rows of iteration 2, where the pipeline starts: f = f0 + 2)
+        const int f0 = wi.y0 - 4, f2 = f0 + 2;
+        unsigned rp1 = (unsigned)wrapi(f2 + 1, (int)ny), r0 = (unsigned)wrapi(f2, (int)ny);
+        unsigned rm1 = (unsigned)wrapi(f2 - 1, (int)ny), rm2 = (unsigned)wrapi(f2 - 2, (int)ny);
+        unsigned rm3 = (unsigned)wrapi(f2 - 3, (int)ny), rm4 = (unsigned)wrapi(f2 - 4, (int)ny);
         // walls: the rows next to them, whose neighbour beyond is a ghost
         const bool walls = WALLS && S.walls != 0;   // the periodic variant has no wall code
         const unsigned ytop = ny - 1u;
@@ -641,12 +642,25 @@ __global__ __launch_bounds__(T, (WALLS || !std::is_same<HT, __half>::value) ? 3 
         };
         Pre preA, preB;
         Carry carA, carB;
+        // Row iterations 0 and 1 would only commit P rows f0 and f0+1 (their stress rows f0-1 and
+        // f0 are read by no stage), so the pipeline starts at iteration 2: those two P rows go
+        // into the ring here, with one wait, and preA takes iteration 2's rows.
         if (live) {
             const unsigned rP0 = r0 * nx * (unsigned)sizeof(PT), NP = N * (unsigned)sizeof(PT);
             const unsigned rS0 = rm1 * nx * 4u, N4 = N * 4u;
             if (POL) {
+                const unsigned rF0 = rm2 * nx * (unsigned)sizeof(PT), rF1 = rm1 * nx * (unsigned)sizeof(PT);
+                PT f00, f01, f10, f11;
+                buf_ld(rPi, bP, rF0, f00);
+                buf_ld(rPi, bP, NP + rF0, f01);
+                buf_ld(rPi, bP, rF1, f10);
+                buf_ld(rPi, bP, NP + rF1, f11);
                 buf_ld(rPi, bP, rP0, preA.P0);
                 buf_ld(rPi, bP, NP + rP0, preA.P1);
+                rP[0][0][tid] = f00;
+                rP[0][1][tid] = f01;
+                rP[1][0][tid] = f10;
+                rP[1][1][tid] = f11;
             }
             preA.S0 = buf_ldf(rSi, b4, rS0);
             preA.S1 = buf_ldf(rSi, b4, N4 + rS0);
@@ -895,7 +909,7 @@ __global__ __launch_bounds__(T, (WALLS || !std::is_same<HT, __half>::value) ? 3 
         // reads make them the slowest) keep the top priority, so they no longer finish last.
         const int lag = (int)gridDim.x <= 4 * cus ? 3 * min(3, (int)blockIdx.x / cus) : 0;
         const int q1 = niter / 3 + lag, q2 = (2 * niter) / 3 + lag;
-        for (int j = 0; j < niter; j += 2) {
+        for (int j = 2; j < niter; j += 2) {
             if (nib != 0)
                 __builtin_amdgcn_s_setprio(3);
             else if (j >= q2)
